@@ -1,0 +1,149 @@
+/*
+ * rte.h -- C ABI of the MI355X FC-DOM time-domain radiative-transfer library.
+ *
+ * The library time-steps the 2-D discrete-ordinates RTE of Gaggioli & Bruno,
+ * "Parallel inverse-problem solver for time-domain optical tomography with
+ * perfect parallel scaling" (arXiv:2202.09421):
+ *
+ *   transport operator, inflow/Fresnel condition ... Sec. 2, eqs. (Toper), (RTE)
+ *   beams, generalised (MSS) sources, detectors ... Sec. 3.1, eqs. (RTEsources),
+ *                                                  (RTEsources2), (OpMed)
+ *   misfit .......................................... Sec. 3.2, eqs. (FObj), (FObjpr)
+ *   adjoint and gradient ............................ Sec. 3.4-3.6, eqs. (AdjointProblem),
+ *                                                  (FDwin22)
+ *   DOM ordinates, normalised HG scattering ......... Sec. 4.1, eq. (RTETrapz)
+ *   AB4 time stepping ............................... Sec. 4.2, eq. (RTEAB4)
+ *   FC-Gram continuation + filtered derivative ...... Sec. 4.3, eqs. (RTEFCSum),
+ *                                                  (FFilter), (RTEFCSumder)
+ *   step loop ....................................... Algorithm 1
+ *
+ * Conventions
+ *   - Units: cm, ps, 1/cm.  The grid has Nx (Ny) intervals, i.e. Nx+1 (Ny+1)
+ *     nodes; node (j, i) sits at (xmin + i*dx, ymin + j*dy).
+ *   - Ordinate m = 0..M-1 has angle 2*pi*m/M.  M must be a multiple of 4.
+ *   - Step n = 0..K-1 advances u^n to u^{n+1} at time t_{n+1} = (n+1)*dt from
+ *     u^0 = 0 with zero AB4 history.
+ *   - Nq generalised sources (MSS combinations, Sec. 3.1) are solved together;
+ *     beam.group selects the combination a beam belongs to.
+ *   - "device" pointers are HIP device memory on the current device; "host"
+ *     pointers are ordinary memory.  All buffers are owned by the caller; the
+ *     plan owns only its immutable tables (allocated in rte_plan_create,
+ *     released in rte_plan_destroy).
+ *   - Every call returns an rte_status.  No C++ exception crosses this ABI.
+ *     On failure rte_last_error() returns a message (thread-local, valid until
+ *     the next call on the same thread).
+ *   - Calls are enqueued on the given hipStream_t (NULL = default stream) and
+ *     return before the GPU finishes unless stated otherwise.  Calls that share
+ *     a plan must not overlap.
+ */
+#ifndef RTE_H
+#define RTE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RTE_OK = 0,
+  RTE_EINVAL = -1,       /* invalid argument or problem description          */
+  RTE_ENOMEM = -2,       /* workspace too small / allocation failed          */
+  RTE_EDEVICE = -3,      /* HIP runtime error                                */
+  RTE_EUNSUPPORTED = -5, /* valid request outside what this build implements */
+  RTE_ESTATE = -6        /* call order violated (e.g. adjoint before forward)*/
+} rte_status;
+
+typedef enum { RTE_F64 = 0, RTE_F32 = 1 } rte_dtype;
+
+/* One problem instance (plain data, host memory, copied by rte_plan_create). */
+typedef struct {
+  int32_t dtype;            /* rte_dtype: precision of states and medium maps      */
+  int32_t reserved0;
+  int64_t Nx, Ny;           /* intervals per side; each side needs >= 2*fc_d nodes */
+  int64_t M;                /* ordinates, multiple of 4                            */
+  int64_t K;                /* time steps                                          */
+  double xmin, xmax, ymin, ymax;
+  double c;                 /* speed of light in the medium, cm/ps                 */
+  double dt;                /* time step, ps                                       */
+  double g;                 /* HG anisotropy, |g| < 1                              */
+  double hg_exponent;       /* 1.5 as printed in eq. (Henyey-Greeinstein)          */
+  double n_in, n_out;       /* refractive indices inside / outside (Fresnel law)   */
+  int64_t fc_d, fc_C;       /* matching points d and blend length C (Sec. 4.3)     */
+  double filt_alpha, filt_beta; /* filter exp(-alpha |2k/Np|^(2 beta)), eq. (FFilter) */
+  const double* fc_Q;       /* host, d*d row-major: Q[k*d+j] = P_j(k), the Gram
+                               basis on the d matching points                     */
+  const double* fc_A;       /* host, C*d row-major: A[p*d+j] = blend of P_j at the
+                               p-th continuation point (Sec. 4.3 step 2)          */
+  int64_t ckpt_every;       /* 0: keep every state u^0..u^K for the adjoint;
+                               s > 0: keep checkpoints every s steps and replay
+                               segments of s steps during the adjoint              */
+} rte_problem;
+
+/* A laser beam, eq. (RTEsources2)/(sourcelab):
+ *   s(x, theta, t) = exp(-|x - (x,y)|^2 / (2 sigma_x^2))
+ *                  * w(d(theta, theta_b) / sigma_theta) * exp(-(t - tau - t0)^2 / (2 sigma_t^2))
+ * with w the window of eq. (sourcelabwind) and d the circular angular distance.
+ * It enters through the inflow condition on the boundary.                    */
+typedef struct {
+  double x, y, theta, sigma_x, sigma_theta, tau, sigma_t, t0;
+  int32_t group;            /* generalised source q (0..Nq-1) this beam fires in */
+  int32_t reserved0;
+} rte_beam;
+
+/* A detector, eq. (OpMed): boundary point and footprint sigma_d (cm). */
+typedef struct { double x, y, sigma_d; } rte_detector;
+
+typedef struct rte_plan rte_plan;
+
+/* Build host tables (ordinates, HG matrix, Fresnel/boundary map, beam and
+ * detector tables, FC multipliers and FFT twiddles) and upload them.
+ * Nq = 1 + max(beam.group).  Errors: RTE_EINVAL for an invalid description
+ * (message says which field), RTE_EDEVICE if the upload fails.           */
+int rte_plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
+                    const rte_detector* dets, int64_t n_det, rte_plan** out);
+int rte_plan_destroy(rte_plan* plan);
+
+/* Queries: Nq, number of detectors, FC extended lengths (x and y lines). */
+int rte_plan_info(const rte_plan* plan, int64_t* Nq, int64_t* Nd, int64_t* Np_x, int64_t* Np_y);
+
+/* Bytes of device workspace needed by rte_forward (+ rte_adjoint when
+ * with_adjoint != 0).  The workspace carries the stored states between a
+ * forward and its adjoint, so the same buffer must be passed to both.     */
+int rte_workspace_bytes(const rte_plan* plan, int with_adjoint, int64_t* bytes);
+
+/* Forward solve, Algorithm 1 for all Nq sources.
+ *   mu_a, mu_s : device, [Ny+1][Nx+1] in the plan dtype: a(x), b(x)
+ *   G          : device out, double [Nq][Nd][K]; G[q][j][n-1] = G_j[u_q](t_n)
+ *   u_final    : device out or NULL, plan dtype [Nq][Ny+1][Nx+1][M] = u^K
+ *   save_states: nonzero keeps what rte_adjoint needs in the workspace
+ *   workspace  : device, >= rte_workspace_bytes(plan, save_states) bytes   */
+int rte_forward(rte_plan* plan, const void* mu_a, const void* mu_s, double* G, void* u_final,
+                int save_states, void* workspace, int64_t workspace_bytes, void* stream);
+
+/* Exact discrete adjoint of the last rte_forward(save_states=1) made with the
+ * same workspace and medium (discrete image of eq. (AdjointProblem)).
+ *   G_bar      : device, double [Nq][Nd][K], the cotangent dJ/dG
+ *   dmu_a/dmu_s: device out, double [Ny+1][Nx+1]: dJ/da_ij, dJ/db_ij summed over
+ *                the Nq sources (discrete eq. (FDwin22) and its b analogue).
+ * RTE_ESTATE if no saved forward is in the workspace.                      */
+int rte_adjoint(rte_plan* plan, const void* mu_a, const void* mu_s, const double* G_bar,
+                double* dmu_a, double* dmu_s, void* workspace, int64_t workspace_bytes, void* stream);
+
+/* Misfit and gradient, eqs. (FObj)/(FObjpr) with the rectangle rule in time:
+ *   J = 1/2 dt sum_q sum_j sum_{n=1..K} (G - G_meas)^2,
+ * followed by the adjoint with G_bar = dt (G - G_meas).
+ *   G_meas : device, double [Nq][Nd][K]
+ *   J      : device out, one double
+ *   G      : device out, double [Nq][Nd][K] (the forward traces)           */
+int rte_gradient(rte_plan* plan, const void* mu_a, const void* mu_s, const double* G_meas,
+                 double* J, double* dmu_a, double* dmu_s, double* G, void* workspace,
+                 int64_t workspace_bytes, void* stream);
+
+/* Thread-local message of the last failed call ("" if none). */
+const char* rte_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTE_H */

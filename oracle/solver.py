@@ -40,7 +40,11 @@ CHI = np.array([55.0, -59.0, 37.0, -9.0]) / 24.0
 
 
 class Oracle:
-    def __init__(self, spec):
+    """dense_derivative=True applies the same FC operators through their dense
+    n x n matrices instead of the FFT: identical mathematics, different rounding
+    order.  Tests use the pair to measure the rounding floor of a quantity."""
+
+    def __init__(self, spec, dense_derivative=False):
         self.spec = s = spec
         if s.M % 2:
             raise ValueError("M must be even")
@@ -59,6 +63,11 @@ class Oracle:
                          for bm in grp] for grp in self.groups]
         self.det = physics.detector_tables(s, self.xs, self.ys)
         self.inflow = None  # optional callable t -> values on the BC entries
+        if dense_derivative:
+            for op in (self.Dx, self.Dy):
+                Dm = op.dense()
+                op.derivative = (lambda D: lambda g, axis=-1: np.moveaxis(np.moveaxis(g, axis, -1) @ D.T, -1, axis))(Dm)
+                op.derivative_T = (lambda D: lambda y, axis=-1: np.moveaxis(np.moveaxis(y, axis, -1) @ D, -1, axis))(Dm)
 
     # ---------------------------------------------------------------- pieces
     def L(self, u, a, b):

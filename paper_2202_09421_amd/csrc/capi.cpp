@@ -1,0 +1,270 @@
+// C ABI entry points: orchestration of the per-step kernels (Algorithm 1 for
+// the forward; the exact discrete adjoint in reverse time; checkpointed
+// segment replay when the states do not all fit).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <sstream>
+
+#include "rte_internal.h"
+
+using namespace rte;
+
+namespace {
+
+#define RTE_CHECK(expr)                                                  \
+  do {                                                                   \
+    hipError_t e_ = (expr);                                              \
+    if (e_ != hipSuccess) {                                              \
+      std::ostringstream o_;                                             \
+      o_ << #expr << ": " << hipGetErrorString(e_);                      \
+      set_error(o_.str());                                               \
+      return RTE_EDEVICE;                                                \
+    }                                                                    \
+  } while (0)
+
+struct Ctx {
+  Plan& p;
+  Workspace& ws;
+  hipStream_t st;
+  const void* mu_a;
+  const void* mu_s;
+  int64_t S;  // state stride in bytes
+};
+
+inline void* at(void* base, int64_t k, int64_t S) { return static_cast<char*>(base) + k * S; }
+
+// One forward step u^n -> u^{n+1}: x lines, y lines, node update.
+int fwd_step(Ctx& c, int n, const void* un, void* unp1, double* flux) {
+  LineLaunch lx{un, nullptr, nullptr, c.ws.tx, LINE_FWD_X, 0, 0.0};
+  RTE_CHECK(launch_line(c.p, lx, c.st));
+  LineLaunch ly{un, c.ws.tx, nullptr, c.ws.tt, LINE_FWD_Y, 1, 0.0};
+  RTE_CHECK(launch_line(c.p, ly, c.st));
+  NodeFwdLaunch nf;
+  nf.u = un;
+  nf.T = c.ws.tt;
+  nf.L1 = c.ws.lring[(n + 2) % 3];
+  nf.L2 = c.ws.lring[(n + 1) % 3];
+  nf.L3 = c.ws.lring[n % 3];
+  nf.mu_a = c.mu_a;
+  nf.mu_s = c.mu_s;
+  nf.u_out = unp1;
+  nf.L_out = c.ws.lring[n % 3];
+  nf.flux = flux;
+  nf.step = n;
+  RTE_CHECK(launch_node_fwd(c.p, nf, c.st));
+  return RTE_OK;
+}
+
+// One adjoint step n (K..1) given u^n.
+int adj_step(Ctx& c, int n, const void* un) {
+  const double cdt = c.p.prob.c * c.p.prob.dt;
+  NodeAdjLaunch na;
+  na.v1 = c.ws.vring[(n + 1) % 4];
+  na.v2 = c.ws.vring[(n + 2) % 4];
+  na.v3 = c.ws.vring[(n + 3) % 4];
+  na.v4 = c.ws.vring[n % 4];
+  na.u = un;
+  na.mu_a = c.mu_a;
+  na.mu_s = c.mu_s;
+  na.inj = c.ws.flux;
+  na.w_out = c.ws.wbuf;
+  na.p_out = c.ws.tt;
+  na.ga = c.ws.ga;
+  na.gb = c.ws.gb;
+  na.step = n;
+  na.convert_v1 = (n + 1 <= c.p.K) ? 1 : 0;
+  RTE_CHECK(launch_node_adj(c.p, na, c.st));
+  LineLaunch lx{c.ws.wbuf, nullptr, nullptr, c.ws.tx, LINE_ADJ_X, 0, cdt};
+  RTE_CHECK(launch_line(c.p, lx, c.st));
+  LineLaunch ly{c.ws.wbuf, c.ws.tx, c.ws.tt, c.ws.vring[n % 4], LINE_ADJ_Y, 1, cdt};
+  RTE_CHECK(launch_line(c.p, ly, c.st));
+  return RTE_OK;
+}
+
+int run_forward(Plan& p, const void* mu_a, const void* mu_s, double* G, void* u_final, int save, void* wsp,
+                int64_t wsb, hipStream_t st) {
+  Workspace ws;
+  if (!map_workspace(p, wsp, wsb, save != 0, &ws)) {
+    std::ostringstream o;
+    o << "workspace too small: need " << workspace_bytes(p, save != 0) << " bytes";
+    set_error(o.str());
+    return RTE_ENOMEM;
+  }
+  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
+  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  Ctx c{p, ws, st, mu_a, mu_s, S};
+  p.have_forward = false;
+  for (int k = 0; k < 3; ++k) RTE_CHECK(hipMemsetAsync(ws.lring[k], 0, S, st));
+  RTE_CHECK(hipMemsetAsync(ws.flux, 0, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
+  const bool store_all = save && p.ckpt_every == 0;
+  const int64_t s = p.ckpt_every;
+  void* u0 = store_all ? ws.states : ws.work_u[0];
+  RTE_CHECK(hipMemsetAsync(u0, 0, S, st));
+  void* un = u0;
+  for (int n = 0; n < p.K; ++n) {
+    if (save && s > 0 && n % s == 0) {
+      void* ck = at(ws.ckpts, (n / s) * 4, S);
+      RTE_CHECK(hipMemcpyAsync(ck, un, S, hipMemcpyDeviceToDevice, st));
+      RTE_CHECK(hipMemcpyAsync(at(ck, 1, S), ws.lring[(n + 2) % 3], S, hipMemcpyDeviceToDevice, st));
+      RTE_CHECK(hipMemcpyAsync(at(ck, 2, S), ws.lring[(n + 1) % 3], S, hipMemcpyDeviceToDevice, st));
+      RTE_CHECK(hipMemcpyAsync(at(ck, 3, S), ws.lring[n % 3], S, hipMemcpyDeviceToDevice, st));
+    }
+    void* unp1 = store_all ? at(ws.states, n + 1, S) : ws.work_u[(n + 1) & 1];
+    int rc = fwd_step(c, n, un, unp1, ws.flux);
+    if (rc != RTE_OK) return rc;
+    un = unp1;
+  }
+  if (G) RTE_CHECK(launch_detect(p, ws.flux, G, (int)p.K, st));
+  if (u_final) RTE_CHECK(launch_unpermute(p, un, u_final, st));
+  p.have_forward = save != 0;
+  p.saved_K = p.K;
+  return RTE_OK;
+}
+
+int run_adjoint(Plan& p, const void* mu_a, const void* mu_s, const double* Gbar, double* da, double* db, void* wsp,
+                int64_t wsb, hipStream_t st) {
+  if (!p.have_forward) {
+    set_error("rte_adjoint needs a preceding rte_forward with save_states=1 on this plan");
+    return RTE_ESTATE;
+  }
+  Workspace ws;
+  if (!map_workspace(p, wsp, wsb, true, &ws)) {
+    std::ostringstream o;
+    o << "workspace too small: need " << workspace_bytes(p, true) << " bytes";
+    set_error(o.str());
+    return RTE_ENOMEM;
+  }
+  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
+  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  Ctx c{p, ws, st, mu_a, mu_s, S};
+  const int K = (int)p.K;
+  RTE_CHECK(launch_inject(p, Gbar, ws.flux, K, st));
+  for (int k = 0; k < 4; ++k) RTE_CHECK(hipMemsetAsync(ws.vring[k], 0, S, st));
+  const int64_t gbytes = p.Nq * p.nx * p.ny * 8;
+  RTE_CHECK(hipMemsetAsync(ws.ga, 0, gbytes, st));
+  RTE_CHECK(hipMemsetAsync(ws.gb, 0, gbytes, st));
+  if (p.ckpt_every == 0) {
+    for (int n = K; n >= 1; --n) {
+      int rc = adj_step(c, n, at(ws.states, n, S));
+      if (rc != RTE_OK) return rc;
+    }
+  } else {
+    const int s = (int)p.ckpt_every;
+    const int nseg = (K + s - 1) / s;
+    for (int j = nseg - 1; j >= 0; --j) {
+      const int k0 = j * s, k1 = std::min(k0 + s, K);
+      void* ck = at(ws.ckpts, (int64_t)j * 4, S);
+      RTE_CHECK(hipMemcpyAsync(ws.states, ck, S, hipMemcpyDeviceToDevice, st));
+      RTE_CHECK(hipMemcpyAsync(ws.lring[(k0 + 2) % 3], at(ck, 1, S), S, hipMemcpyDeviceToDevice, st));
+      RTE_CHECK(hipMemcpyAsync(ws.lring[(k0 + 1) % 3], at(ck, 2, S), S, hipMemcpyDeviceToDevice, st));
+      RTE_CHECK(hipMemcpyAsync(ws.lring[k0 % 3], at(ck, 3, S), S, hipMemcpyDeviceToDevice, st));
+      for (int k = k0; k < k1; ++k) {
+        int rc = fwd_step(c, k, at(ws.states, k - k0, S), at(ws.states, k + 1 - k0, S), nullptr);
+        if (rc != RTE_OK) return rc;
+      }
+      for (int n = k1; n > k0; --n) {
+        int rc = adj_step(c, n, at(ws.states, n - k0, S));
+        if (rc != RTE_OK) return rc;
+      }
+    }
+  }
+  RTE_CHECK(launch_grad_reduce(p, ws.ga, ws.gb, da, db, st));
+  return RTE_OK;
+}
+
+bool nonnull(const void* p, const char* what) {
+  if (!p) {
+    set_error(std::string(what) + " is NULL");
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rte_plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams, const rte_detector* dets,
+                    int64_t n_det, rte_plan** out) {
+  try {
+    set_error("");
+    return plan_create(prob, beams, n_beams, dets, n_det, out);
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RTE_EINVAL;
+  }
+}
+
+int rte_plan_destroy(rte_plan* plan) { return plan_destroy(plan); }
+
+int rte_plan_info(const rte_plan* h, int64_t* Nq, int64_t* Nd, int64_t* Npx, int64_t* Npy) {
+  if (!nonnull(h, "plan")) return RTE_EINVAL;
+  const Plan& p = *reinterpret_cast<const Plan*>(h);
+  if (Nq) *Nq = p.Nq;
+  if (Nd) *Nd = p.Nd;
+  if (Npx) *Npx = p.fcx.Np;
+  if (Npy) *Npy = p.fcy.Np;
+  return RTE_OK;
+}
+
+int rte_workspace_bytes(const rte_plan* h, int with_adjoint, int64_t* bytes) {
+  if (!nonnull(h, "plan") || !nonnull(bytes, "bytes")) return RTE_EINVAL;
+  *bytes = workspace_bytes(*reinterpret_cast<const Plan*>(h), with_adjoint != 0);
+  return RTE_OK;
+}
+
+int rte_forward(rte_plan* h, const void* mu_a, const void* mu_s, double* G, void* u_final, int save_states,
+                void* workspace, int64_t workspace_bytes, void* stream) {
+  if (!nonnull(h, "plan") || !nonnull(mu_a, "mu_a") || !nonnull(mu_s, "mu_s") || !nonnull(workspace, "workspace"))
+    return RTE_EINVAL;
+  try {
+    set_error("");
+    return run_forward(*reinterpret_cast<Plan*>(h), mu_a, mu_s, G, u_final, save_states, workspace, workspace_bytes,
+                       static_cast<hipStream_t>(stream));
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RTE_EINVAL;
+  }
+}
+
+int rte_adjoint(rte_plan* h, const void* mu_a, const void* mu_s, const double* G_bar, double* dmu_a, double* dmu_s,
+                void* workspace, int64_t workspace_bytes, void* stream) {
+  if (!nonnull(h, "plan") || !nonnull(mu_a, "mu_a") || !nonnull(mu_s, "mu_s") || !nonnull(G_bar, "G_bar") ||
+      !nonnull(dmu_a, "dmu_a") || !nonnull(dmu_s, "dmu_s") || !nonnull(workspace, "workspace"))
+    return RTE_EINVAL;
+  try {
+    set_error("");
+    return run_adjoint(*reinterpret_cast<Plan*>(h), mu_a, mu_s, G_bar, dmu_a, dmu_s, workspace, workspace_bytes,
+                       static_cast<hipStream_t>(stream));
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RTE_EINVAL;
+  }
+}
+
+int rte_gradient(rte_plan* h, const void* mu_a, const void* mu_s, const double* G_meas, double* J, double* dmu_a,
+                 double* dmu_s, double* G, void* workspace, int64_t workspace_bytes, void* stream) {
+  if (!nonnull(h, "plan") || !nonnull(mu_a, "mu_a") || !nonnull(mu_s, "mu_s") || !nonnull(G_meas, "G_meas") ||
+      !nonnull(J, "J") || !nonnull(dmu_a, "dmu_a") || !nonnull(dmu_s, "dmu_s") || !nonnull(G, "G") ||
+      !nonnull(workspace, "workspace"))
+    return RTE_EINVAL;
+  try {
+    set_error("");
+    Plan& p = *reinterpret_cast<Plan*>(h);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = run_forward(p, mu_a, mu_s, G, nullptr, 1, workspace, workspace_bytes, st);
+    if (rc != RTE_OK) return rc;
+    Workspace ws;
+    map_workspace(p, workspace, workspace_bytes, true, &ws);
+    RTE_CHECK(launch_misfit(p, G, G_meas, ws.gbar, J, (int)p.K, st));
+    return run_adjoint(p, mu_a, mu_s, ws.gbar, dmu_a, dmu_s, workspace, workspace_bytes, st);
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RTE_EINVAL;
+  }
+}
+
+const char* rte_last_error(void) { return last_error(); }
+
+}  // extern "C"

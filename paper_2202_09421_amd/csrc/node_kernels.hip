@@ -1,0 +1,519 @@
+// Node passes of the FC-DOM step and its adjoint, plus the small detector,
+// misfit and gradient kernels.
+//
+// Forward node pass (Sec. 4.1-4.2, eq. RTEAB4; Algorithm 1 "right hand side"
+// and "impose boundary conditions"): for a tile of nodes with all M ordinates,
+//   S    = W u                       HG scattering, a dense M x M contraction
+//                                    per node, on FP64/FP32 MFMA 16x16x4
+//   L^n  = b S - (a + b) u + T       T = -xi Dx u - eta Dy u from the line passes
+//   u~   = u + c dt (chi0 L^n + chi1 L^{n-1} + chi2 L^{n-2} + chi3 L^{n-3})
+//   u^{n+1} = f u~(reflected slot) + q(x_b, t_{n+1}) on incoming boundary
+//             entries (eq. RTE, last line), u~ elsewhere
+//   flux[w][pos] = sum_m kappa_w(m) u^{n+1}_m on boundary nodes (eq. OpMed)
+//
+// Adjoint node pass (exact transpose, reverse time): with v^k = P^T ubar^k,
+//   w^n  = sum_l chi_l v^{n+1+l}
+//   P1   = v^{n+1} + c dt (b W w - (a + b) w) + D_e^T Gbar^n
+//   dJ/da += -c dt sum_m u^n_m w_m,   dJ/db += c dt sum_m u^n_m ((W w)_m - w_m)
+// The line passes then add -c dt (Dx^T(xi w) + Dy^T(eta w)) to P1.
+#include "rte_internal.h"
+
+namespace rte {
+
+constexpr double kChi0 = 55.0 / 24.0, kChi1 = -59.0 / 24.0, kChi2 = 37.0 / 24.0, kChi3 = -9.0 / 24.0;
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+// Operands of both 16x16x4 variants: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16].  Result element v of lane l is D[row][l%16] with
+// row = l/16 + 4v for FP64 and row = 4(l/16) + v for FP32 (gfx950, measured).
+template <>
+struct Mfma<double> {
+  typedef d4v acc_t;
+  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef f4v acc_t;
+  static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
+};
+
+struct NodeGeom {
+  int nx, ny, M, Mpad, G, nb, npos, K1;
+  int64_t grp_stride, inst_stride;
+};
+
+__device__ __forceinline__ int node_type(int j, int i, int nx, int ny) {
+  const int tx = (i == 0) ? 1 : ((i == nx - 1) ? 2 : 0);
+  const int ty = (j == 0) ? 1 : ((j == ny - 1) ? 2 : 0);
+  return tx + 3 * ty;
+}
+
+__device__ __forceinline__ int boundary_pos(int j, int i, int nx, int ny) {
+  if (j == 0) return i;
+  if (j == ny - 1) return nx + i;
+  if (i == 0) return 2 * nx + j - 1;
+  return 2 * nx + (ny - 2) + j - 1;
+}
+
+// S[node][s] = sum_s' X[node][s'] W[s'][s] for TN nodes; X and S in LDS with
+// row stride LS.  16x16x4 MFMA: A = 16 nodes x 4 slots, B = 4 slots x 16 slots.
+template <typename T, int TN>
+__device__ __forceinline__ void scatter_mfma(const T* X, T* S, int LS, const double* __restrict__ Wt, int Mpad) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int RB = TN / 16;            // row blocks
+  constexpr int WPR = 4 / RB;            // waves sharing a row block
+  const int rb = wave % RB;
+  const int row = 16 * rb + (lane & 15);
+  const int kq = lane >> 4;
+  const int ntile = Mpad / 16;
+  for (int t = wave / RB; t < ntile; t += WPR) {
+    acc_t acc = {0, 0, 0, 0};
+    for (int kc = 0; kc < Mpad / 4; ++kc) {
+      const T av = X[row * LS + 4 * kc + kq];
+      const T bv = T(Wt[(4 * kc + kq) * Mpad + 16 * t + (lane & 15)]);
+      acc = Mfma<T>::step(av, bv, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[(16 * rb + Mfma<T>::row(kq, v)) * LS + 16 * t + (lane & 15)] = acc[v];
+  }
+}
+
+// ---------------------------------------------------------------- forward
+template <typename T>
+struct NodeFwdArgs {
+  const T* u; const T* Tt; const T* L1; const T* L2; const T* L3;
+  const T* mu_a; const T* mu_s;
+  T* u_out; T* L_out; double* flux;
+  const double* Wt; const BcRule* bc; const double* kappa;
+  const double* beam_sp; const double* beam_an; const double* beam_tt; const int32_t* beam_off;
+  NodeGeom geo;
+  int step;
+  double cdt;
+};
+
+template <typename T, int TN>
+__global__ __launch_bounds__(kNodeThreads) void node_fwd_kernel(NodeFwdArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const NodeGeom& G = a.geo;
+  const int LS = G.Mpad + 1;
+  T* Us = reinterpret_cast<T*>(smem_raw);
+  T* Ss = Us + TN * LS;
+  T* As = Ss + TN * LS;
+  T* Bs = As + TN;
+  const int tid = threadIdx.x;
+  const int q = blockIdx.y;
+  const int Nn = G.nx * G.ny;
+  const int node0 = blockIdx.x * TN;
+  const int64_t ib = (int64_t)q * G.inst_stride;
+  const int nel = G.G * TN * kGroup;
+
+  // 1. stage u^n, a, b
+  for (int e = tid; e < nel; e += kNodeThreads) {
+    const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
+    const int gn = node0 + nd;
+    Us[nd * LS + g * kGroup + r] = (gn < Nn) ? a.u[ib + g * G.grp_stride + (int64_t)gn * kGroup + r] : T(0);
+  }
+  for (int e = tid; e < TN * (G.Mpad - G.M); e += kNodeThreads) {
+    const int nd = e / (G.Mpad - G.M), s = G.M + e % (G.Mpad - G.M);
+    Us[nd * LS + s] = T(0);
+  }
+  for (int nd = tid; nd < TN; nd += kNodeThreads) {
+    const int gn = node0 + nd;
+    As[nd] = (gn < Nn) ? a.mu_a[gn] : T(0);
+    Bs[nd] = (gn < Nn) ? a.mu_s[gn] : T(0);
+  }
+  __syncthreads();
+
+  // 2. scattering on MFMA
+  scatter_mfma<T, TN>(Us, Ss, LS, a.Wt, G.Mpad);
+  __syncthreads();
+
+  // 3. L^n and the AB4 combination
+  const T cdt = T(a.cdt);
+  for (int e = tid; e < nel; e += kNodeThreads) {
+    const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
+    const int gn = node0 + nd;
+    if (gn >= Nn) continue;
+    const int s = g * kGroup + r;
+    const int64_t off = ib + g * G.grp_stride + (int64_t)gn * kGroup + r;
+    const T uu = Us[nd * LS + s];
+    const T Ln = Bs[nd] * Ss[nd * LS + s] - (As[nd] + Bs[nd]) * uu + a.Tt[off];
+    const T l1 = a.L1[off], l2 = a.L2[off], l3 = a.L3[off];
+    const T ut = uu + cdt * (T(kChi0) * Ln + T(kChi1) * l1 + T(kChi2) * l2 + T(kChi3) * l3);
+    a.L_out[off] = Ln;
+    Ss[nd * LS + s] = ut;
+  }
+  __syncthreads();
+
+  // 4. inflow condition with Fresnel reflection and the beams at t_{n+1}
+  for (int e = tid; e < nel; e += kNodeThreads) {
+    const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
+    const int gn = node0 + nd;
+    if (gn >= Nn) continue;
+    const int s = g * kGroup + r;
+    const int j = gn / G.nx, i = gn - j * G.nx;
+    const int ty = node_type(j, i, G.nx, G.ny);
+    T val = Ss[nd * LS + s];
+    if (ty != 0) {
+      const BcRule br = a.bc[ty * G.M + s];
+      if (br.flag) {
+        val = T(br.coef_a) * Ss[nd * LS + br.src_a] + T(br.coef_b) * Ss[nd * LS + br.src_b];
+        const int bp = boundary_pos(j, i, G.nx, G.ny);
+        for (int k = a.beam_off[q]; k < a.beam_off[q + 1]; ++k)
+          val += T(a.beam_sp[(int64_t)k * G.nb + bp] * a.beam_an[k * G.M + s]) * T(a.beam_tt[(int64_t)k * G.K1 + a.step + 1]);
+      }
+    }
+    a.u_out[ib + g * G.grp_stride + (int64_t)gn * kGroup + r] = val;
+    Us[nd * LS + s] = val;
+  }
+  if (a.flux == nullptr) return;
+  __syncthreads();
+
+  // 5. detector flux on boundary nodes (FP64 accumulation)
+  for (int nd = tid; nd < TN; nd += kNodeThreads) {
+    const int gn = node0 + nd;
+    if (gn >= Nn) continue;
+    const int j = gn / G.nx, i = gn - j * G.nx;
+    int walls[2], nw = 0;
+    if (i == 0) walls[nw++] = 0;
+    if (i == G.nx - 1) walls[nw++] = 1;
+    if (j == 0) walls[nw++] = 2;
+    if (j == G.ny - 1) walls[nw++] = 3;
+    for (int t = 0; t < nw; ++t) {
+      const int w = walls[t];
+      double acc = 0.0;
+      for (int s = 0; s < G.M; ++s) acc += a.kappa[w * G.M + s] * (double)Us[nd * LS + s];
+      const int pos = (w < 2) ? j : i;
+      a.flux[(((int64_t)q * G.K1 + a.step + 1) * 4 + w) * G.npos + pos] = acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- adjoint
+template <typename T>
+struct NodeAdjArgs {
+  T* v1; const T* v2; const T* v3; const T* v4; const T* u;
+  const T* mu_a; const T* mu_s; const double* inj;
+  T* w_out; T* p_out; double* ga; double* gb;
+  const double* Wt; const BcRuleT* bct; const double* kappa;
+  NodeGeom geo;
+  int step;
+  int convert_v1;
+  double cdt;
+};
+
+template <typename T, int TN>
+__global__ __launch_bounds__(kNodeThreads) void node_adj_kernel(NodeAdjArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const NodeGeom& G = a.geo;
+  const int LS = G.Mpad + 1;
+  T* Vb = reinterpret_cast<T*>(smem_raw);
+  T* Wb = Vb + TN * LS;
+  T* Sb = Wb + TN * LS;
+  T* As = Sb + TN * LS;
+  T* Bs = As + TN;
+  const int tid = threadIdx.x;
+  const int q = blockIdx.y;
+  const int Nn = G.nx * G.ny;
+  const int node0 = blockIdx.x * TN;
+  const int64_t ib = (int64_t)q * G.inst_stride;
+  const int nel = G.G * TN * kGroup;
+
+  for (int e = tid; e < nel; e += kNodeThreads) {
+    const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
+    const int gn = node0 + nd;
+    Vb[nd * LS + g * kGroup + r] = (gn < Nn) ? a.v1[ib + g * G.grp_stride + (int64_t)gn * kGroup + r] : T(0);
+  }
+  for (int nd = tid; nd < TN; nd += kNodeThreads) {
+    const int gn = node0 + nd;
+    As[nd] = (gn < Nn) ? a.mu_a[gn] : T(0);
+    Bs[nd] = (gn < Nn) ? a.mu_s[gn] : T(0);
+  }
+  __syncthreads();
+
+  // 1. v^{n+1} = P^T ubar^{n+1} on boundary nodes (in place)
+  if (a.convert_v1) {
+    for (int e = tid; e < nel; e += kNodeThreads) {
+      const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
+      const int gn = node0 + nd;
+      if (gn >= Nn) continue;
+      const int s = g * kGroup + r;
+      const int j = gn / G.nx, i = gn - j * G.nx;
+      const int ty = node_type(j, i, G.nx, G.ny);
+      if (ty == 0) continue;
+      const BcRuleT rt = a.bct[ty * G.M + s];
+      T val = rt.is_target ? T(0) : Vb[nd * LS + s];
+      for (int t = 0; t < rt.ntgt; ++t) val += T(rt.coef[t]) * Vb[nd * LS + rt.tgt[t]];
+      Sb[nd * LS + s] = val;
+    }
+    __syncthreads();
+    for (int e = tid; e < nel; e += kNodeThreads) {
+      const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
+      const int gn = node0 + nd;
+      if (gn >= Nn) continue;
+      const int j = gn / G.nx, i = gn - j * G.nx;
+      if (node_type(j, i, G.nx, G.ny) == 0) continue;
+      const int s = g * kGroup + r;
+      const T val = Sb[nd * LS + s];
+      Vb[nd * LS + s] = val;
+      a.v1[ib + g * G.grp_stride + (int64_t)gn * kGroup + r] = val;
+    }
+    __syncthreads();
+  }
+
+  // 2. w^n
+  for (int e = tid; e < nel; e += kNodeThreads) {
+    const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
+    const int gn = node0 + nd;
+    const int s = g * kGroup + r;
+    T w = T(0);
+    if (gn < Nn) {
+      const int64_t off = ib + g * G.grp_stride + (int64_t)gn * kGroup + r;
+      w = T(kChi0) * Vb[nd * LS + s] + T(kChi1) * a.v2[off] + T(kChi2) * a.v3[off] + T(kChi3) * a.v4[off];
+    }
+    Wb[nd * LS + s] = w;
+  }
+  for (int e = tid; e < TN * (G.Mpad - G.M); e += kNodeThreads) {
+    const int nd = e / (G.Mpad - G.M), s = G.M + e % (G.Mpad - G.M);
+    Wb[nd * LS + s] = T(0);
+  }
+  __syncthreads();
+
+  // 3. W w on MFMA (W is symmetric)
+  scatter_mfma<T, TN>(Wb, Sb, LS, a.Wt, G.Mpad);
+  __syncthreads();
+
+  // 4. P1, w and the gradient products
+  const T cdt = T(a.cdt);
+  for (int e = tid; e < nel; e += kNodeThreads) {
+    const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
+    const int gn = node0 + nd;
+    if (gn >= Nn) continue;
+    const int s = g * kGroup + r;
+    const int64_t off = ib + g * G.grp_stride + (int64_t)gn * kGroup + r;
+    const T w = Wb[nd * LS + s], S = Sb[nd * LS + s];
+    T p1 = Vb[nd * LS + s] + cdt * (Bs[nd] * S - (As[nd] + Bs[nd]) * w);
+    const int j = gn / G.nx, i = gn - j * G.nx;
+    if (node_type(j, i, G.nx, G.ny) != 0) {
+      // detector misfit enters through the outgoing boundary entries
+      if (i == 0) p1 += T(a.kappa[0 * G.M + s] * a.inj[(((int64_t)q * G.K1 + a.step) * 4 + 0) * G.npos + j]);
+      if (i == G.nx - 1) p1 += T(a.kappa[1 * G.M + s] * a.inj[(((int64_t)q * G.K1 + a.step) * 4 + 1) * G.npos + j]);
+      if (j == 0) p1 += T(a.kappa[2 * G.M + s] * a.inj[(((int64_t)q * G.K1 + a.step) * 4 + 2) * G.npos + i]);
+      if (j == G.ny - 1) p1 += T(a.kappa[3 * G.M + s] * a.inj[(((int64_t)q * G.K1 + a.step) * 4 + 3) * G.npos + i]);
+    }
+    a.p_out[off] = p1;
+    a.w_out[off] = w;
+    const T un = a.u[off];
+    Vb[nd * LS + s] = un * w;
+    Sb[nd * LS + s] = un * (S - w);
+  }
+  __syncthreads();
+
+  // 5. per-node gradient sums (fixed order: deterministic)
+  for (int nd = tid; nd < TN; nd += kNodeThreads) {
+    const int gn = node0 + nd;
+    if (gn >= Nn) continue;
+    double sa = 0.0, sb = 0.0;
+    for (int s = 0; s < G.M; ++s) {
+      sa += (double)Vb[nd * LS + s];
+      sb += (double)Sb[nd * LS + s];
+    }
+    a.ga[(int64_t)q * Nn + gn] -= a.cdt * sa;
+    a.gb[(int64_t)q * Nn + gn] += a.cdt * sb;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static NodeGeom make_geom(const Plan& p) {
+  NodeGeom g;
+  g.nx = (int)p.nx; g.ny = (int)p.ny; g.M = (int)p.M; g.Mpad = (int)p.Mpad; g.G = (int)p.G;
+  g.nb = (int)p.nb; g.npos = (int)p.npos; g.K1 = (int)(p.K + 1);
+  g.grp_stride = p.ny * p.nx * kGroup;
+  g.inst_stride = p.G * g.grp_stride;
+  return g;
+}
+
+template <typename T>
+static int node_tile(const Plan& p) { return (p.Mpad * sizeof(T) <= 256) ? 64 : 32; }
+
+template <typename T>
+static hipError_t node_fwd_t(const Plan& p, const NodeFwdLaunch& L, hipStream_t s) {
+  NodeFwdArgs<T> a;
+  a.u = (const T*)L.u; a.Tt = (const T*)L.T; a.L1 = (const T*)L.L1; a.L2 = (const T*)L.L2; a.L3 = (const T*)L.L3;
+  a.mu_a = (const T*)L.mu_a; a.mu_s = (const T*)L.mu_s;
+  a.u_out = (T*)L.u_out; a.L_out = (T*)L.L_out; a.flux = L.flux;
+  a.Wt = p.dev.Wt; a.bc = p.dev.bc; a.kappa = p.dev.kappa;
+  a.beam_sp = p.dev.beam_sp; a.beam_an = p.dev.beam_an; a.beam_tt = p.dev.beam_tt; a.beam_off = p.dev.beam_off;
+  a.geo = make_geom(p);
+  a.step = L.step;
+  a.cdt = p.prob.c * p.prob.dt;
+  const int TN = node_tile<T>(p);
+  const int Nn = (int)(p.nx * p.ny);
+  dim3 grid((unsigned)((Nn + TN - 1) / TN), (unsigned)p.Nq);
+  const size_t sh = sizeof(T) * (size_t)(2 * TN * (p.Mpad + 1) + 2 * TN);
+  if (TN == 64) hipLaunchKernelGGL((node_fwd_kernel<T, 64>), grid, dim3(kNodeThreads), sh, s, a);
+  else hipLaunchKernelGGL((node_fwd_kernel<T, 32>), grid, dim3(kNodeThreads), sh, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_fwd(const Plan& p, const NodeFwdLaunch& L, hipStream_t s) {
+  return p.dtype == RTE_F64 ? node_fwd_t<double>(p, L, s) : node_fwd_t<float>(p, L, s);
+}
+
+template <typename T>
+static hipError_t node_adj_t(const Plan& p, const NodeAdjLaunch& L, hipStream_t s) {
+  NodeAdjArgs<T> a;
+  a.v1 = (T*)L.v1; a.v2 = (const T*)L.v2; a.v3 = (const T*)L.v3; a.v4 = (const T*)L.v4; a.u = (const T*)L.u;
+  a.mu_a = (const T*)L.mu_a; a.mu_s = (const T*)L.mu_s; a.inj = L.inj;
+  a.w_out = (T*)L.w_out; a.p_out = (T*)L.p_out; a.ga = L.ga; a.gb = L.gb;
+  a.Wt = p.dev.Wt; a.bct = p.dev.bct; a.kappa = p.dev.kappa;
+  a.geo = make_geom(p);
+  a.step = L.step;
+  a.convert_v1 = L.convert_v1;
+  a.cdt = p.prob.c * p.prob.dt;
+  const int TN = node_tile<T>(p);
+  const int Nn = (int)(p.nx * p.ny);
+  dim3 grid((unsigned)((Nn + TN - 1) / TN), (unsigned)p.Nq);
+  const size_t sh = sizeof(T) * (size_t)(3 * TN * (p.Mpad + 1) + 2 * TN);
+  if (TN == 64) hipLaunchKernelGGL((node_adj_kernel<T, 64>), grid, dim3(kNodeThreads), sh, s, a);
+  else hipLaunchKernelGGL((node_adj_kernel<T, 32>), grid, dim3(kNodeThreads), sh, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_adj(const Plan& p, const NodeAdjLaunch& L, hipStream_t s) {
+  return p.dtype == RTE_F64 ? node_adj_t<double>(p, L, s) : node_adj_t<float>(p, L, s);
+}
+
+// G[q][jd][k] = sum_{w,pos} det_w[jd][w][pos] flux[q][k+1][w][pos]
+__global__ void detect_kernel(const double* __restrict__ flux, const double* __restrict__ dw, double* __restrict__ G,
+                              int Nq, int Nd, int K, int npos) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)Nq * Nd * K;
+  if (t >= total) return;
+  const int k = (int)(t % K);
+  const int jd = (int)((t / K) % Nd);
+  const int q = (int)(t / ((int64_t)K * Nd));
+  const double* f = flux + ((int64_t)q * (K + 1) + k + 1) * 4 * npos;
+  const double* w = dw + (int64_t)jd * 4 * npos;
+  double acc = 0.0;
+  for (int x = 0; x < 4 * npos; ++x) acc += w[x] * f[x];
+  G[t] = acc;
+}
+
+// inj[q][n][w][pos] = sum_jd det_w[jd][w][pos] Gbar[q][jd][n-1], n = 1..K
+__global__ void inject_kernel(const double* __restrict__ Gbar, const double* __restrict__ dw, double* __restrict__ inj,
+                              int Nq, int Nd, int K, int npos) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)K * 4 * npos;
+  if (t >= (int64_t)Nq * per) return;
+  const int q = (int)(t / per);
+  const int64_t r = t % per;
+  const int n = 1 + (int)(r / (4 * npos));
+  const int x = (int)(r % (4 * npos));
+  double acc = 0.0;
+  for (int jd = 0; jd < Nd; ++jd) acc += dw[(int64_t)jd * 4 * npos + x] * Gbar[((int64_t)q * Nd + jd) * K + n - 1];
+  inj[((int64_t)q * (K + 1) + n) * 4 * npos + x] = acc;
+}
+
+// Gbar = dt (G - Gm); J = 1/2 dt sum (G - Gm)^2 (one block, fixed reduction order)
+__global__ __launch_bounds__(1024) void misfit_kernel(const double* __restrict__ G, const double* __restrict__ Gm,
+                                                      double* __restrict__ Gbar, double* __restrict__ J, int64_t n,
+                                                      double dt) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < n; t += 1024) {
+    const double r = G[t] - Gm[t];
+    Gbar[t] = dt * r;
+    acc += r * r;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *J = 0.5 * dt * red[0];
+}
+
+__global__ void grad_reduce_kernel(const double* __restrict__ ga, const double* __restrict__ gb, double* __restrict__ da,
+                                   double* __restrict__ db, int Nq, int64_t Nn) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Nn) return;
+  double sa = 0.0, sb = 0.0;
+  for (int q = 0; q < Nq; ++q) {
+    sa += ga[(int64_t)q * Nn + t];
+    sb += gb[(int64_t)q * Nn + t];
+  }
+  da[t] = sa;
+  db[t] = sb;
+}
+
+template <typename T>
+__global__ void unpermute_kernel(const T* __restrict__ st, T* __restrict__ out, const int32_t* __restrict__ slot_m,
+                                 int M, int G, int64_t Nn, int Nq) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)Nq * Nn * M;
+  if (t >= total) return;
+  const int s = (int)(t % M);
+  const int64_t gn = (t / M) % Nn;
+  const int q = (int)(t / (M * Nn));
+  const int g = s / kGroup, r = s % kGroup;
+  const T v = st[(int64_t)q * G * Nn * kGroup + (int64_t)g * Nn * kGroup + gn * kGroup + r];
+  out[((int64_t)q * Nn + gn) * M + slot_m[s]] = v;
+}
+
+hipError_t launch_detect(const Plan& p, const double* flux, double* G, int K, hipStream_t s) {
+  const int64_t total = p.Nq * p.Nd * K;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(detect_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, flux, p.dev.det_w, G,
+                     (int)p.Nq, (int)p.Nd, K, (int)p.npos);
+  return hipGetLastError();
+}
+
+hipError_t launch_inject(const Plan& p, const double* Gbar, double* inj, int K, hipStream_t s) {
+  const int64_t total = p.Nq * (int64_t)K * 4 * p.npos;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(inject_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, Gbar, p.dev.det_w, inj,
+                     (int)p.Nq, (int)p.Nd, K, (int)p.npos);
+  return hipGetLastError();
+}
+
+hipError_t launch_misfit(const Plan& p, const double* G, const double* Gm, double* Gbar, double* J, int K,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(1024), 0, s, G, Gm, Gbar, J, p.Nq * p.Nd * (int64_t)K, p.prob.dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const Plan& p, const double* ga, const double* gb, double* da, double* db,
+                              hipStream_t s) {
+  const int64_t Nn = p.nx * p.ny;
+  hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)((Nn + 255) / 256)), dim3(256), 0, s, ga, gb, da, db,
+                     (int)p.Nq, Nn);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpermute(const Plan& p, const void* state, void* out, hipStream_t s) {
+  const int64_t Nn = p.nx * p.ny;
+  const int64_t total = p.Nq * Nn * p.M;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (p.dtype == RTE_F64)
+    hipLaunchKernelGGL(unpermute_kernel<double>, grid, dim3(256), 0, s, (const double*)state, (double*)out,
+                       p.dev.slot_m, (int)p.M, (int)p.G, Nn, (int)p.Nq);
+  else
+    hipLaunchKernelGGL(unpermute_kernel<float>, grid, dim3(256), 0, s, (const float*)state, (float*)out,
+                       p.dev.slot_m, (int)p.M, (int)p.G, Nn, (int)p.Nq);
+  return hipGetLastError();
+}
+
+}  // namespace rte

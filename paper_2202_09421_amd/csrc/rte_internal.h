@@ -1,0 +1,175 @@
+// Internal declarations shared by the host plan code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rte.h"
+
+namespace rte {
+
+constexpr int kGroup = 4;        // ordinate slots per storage group (one reflection orbit)
+constexpr int kMaxPasses = 12;   // FFT passes (radices 2,3,4,5)
+constexpr int kMaxFcD = 8;       // matching points supported
+constexpr int kNodeTile = 64;    // nodes per node-pass workgroup
+constexpr int kNodeThreads = 256;
+constexpr int kLineThreads = 128;
+
+void set_error(const std::string& msg);
+const char* last_error();
+int plan_create(const rte_problem*, const rte_beam*, int64_t, const rte_detector*, int64_t, rte_plan**);
+int plan_destroy(rte_plan*);
+size_t line_shmem_bytes(int Np, int dtype);
+
+// FC-Gram derivative plan for one line direction (device pointers inside).
+struct FcPlanDev {
+  int n;        // nodes per line
+  int Np;       // extended length n + C + E
+  int E, d, C;
+  int npass;
+  int radix[kMaxPasses];
+  int ns[kMaxPasses];       // Stockham sub-transform length before the pass
+  int twoff[kMaxPasses];    // offset (complex entries) into the twiddle table
+  const double* tw;         // complex twiddles, interleaved (re, im), FP64
+  const double* mu;         // Np real multipliers: derivative factor * filter / Np
+  const double* Q;          // d*d
+  const double* A;          // C*d
+};
+
+// Per-slot boundary rule for one node type (9 types: interior, 4 edges, 4 corners).
+struct BcRule {
+  int32_t flag;     // 1 if (node type, slot) is overwritten by the inflow condition
+  int32_t src_a, src_b;
+  int32_t pad;
+  double coef_a, coef_b;
+};
+
+// Transpose of the boundary map: for source slot s', the targets it feeds.
+struct BcRuleT {
+  int32_t is_target;   // slot is overwritten (its own value does not pass through)
+  int32_t ntgt;
+  int32_t tgt[2];
+  double coef[2];
+};
+
+struct DeviceTables {
+  // ordinates in storage order (slot s = 4*g + r)
+  double* xi = nullptr;     // [M]
+  double* eta = nullptr;    // [M]
+  double* Wt = nullptr;     // [Mpad16][Mpad16] HG matrix in slot order (zero padded)
+  BcRule* bc = nullptr;     // [9][M]
+  BcRuleT* bct = nullptr;   // [9][M]
+  double* kappa = nullptr;  // [4][M] detector factor per wall and slot
+  double* det_w = nullptr;  // [Nd][4][npos] detector weights
+  // beams: per beam spatial (boundary position) and angular (slot) factors, temporal samples
+  double* beam_sp = nullptr;   // [nbeams][nb]
+  double* beam_an = nullptr;   // [nbeams][M]
+  double* beam_tt = nullptr;   // [nbeams][K+1]
+  int32_t* beam_off = nullptr; // [Nq+1] CSR offsets of beams per source
+  int32_t* slot_m = nullptr;   // [M] slot -> ordinate index
+  double* fc_buf = nullptr;    // FC tables of both directions
+};
+
+struct Plan {
+  rte_problem prob{};
+  int dtype = RTE_F64;
+  int64_t nx = 0, ny = 0, M = 0, G = 0, Mpad = 0, K = 0, Nq = 0, Nd = 0, nbeams = 0;
+  int64_t nb = 0;     // boundary nodes 2(nx+ny)-4
+  int64_t npos = 0;   // max(nx, ny)
+  std::vector<int> slot_m;  // slot -> ordinate index
+  FcPlanDev fcx{}, fcy{};
+  DeviceTables dev;
+  int64_t ckpt_every = 0;
+  bool have_forward = false;   // a saved forward lives in the workspace
+  int64_t saved_K = 0;
+};
+
+// ---------------------------------------------------------------- workspace map
+struct Workspace {
+  char* base = nullptr;
+  int64_t bytes = 0;
+  // state-sized arrays (plan dtype), each Nq*M*ny*nx elements
+  void* states = nullptr;    // store-all: (K+1) states; checkpoint: segment store (s+1)
+  void* ckpts = nullptr;     // checkpoint mode: n_ckpt * 4 states (u, L1, L2, L3)
+  void* work_u[2] = {nullptr, nullptr};  // checkpoint mode: ping-pong current state
+  void* lring[3] = {nullptr, nullptr, nullptr};
+  void* tx = nullptr;        // line-pass intermediate
+  void* tt = nullptr;        // second intermediate (T, or adjoint P1)
+  void* vring[4] = {nullptr, nullptr, nullptr, nullptr};  // adjoint ring
+  void* wbuf = nullptr;      // adjoint w
+  double* flux = nullptr;    // [Nq][K+1][4][npos] detector flux / adjoint injection
+  double* ga = nullptr;      // [Nq][ny*nx]
+  double* gb = nullptr;
+  double* gbar = nullptr;    // [Nq][Nd][K] misfit cotangent (rte_gradient)
+  double* scratch = nullptr; // small reductions
+};
+
+int64_t state_elems(const Plan& p);
+int64_t workspace_bytes(const Plan& p, bool with_adjoint);
+bool map_workspace(const Plan& p, void* base, int64_t bytes, bool with_adjoint, Workspace* ws);
+
+// ---------------------------------------------------------------- kernel launchers
+enum LineMode {
+  LINE_FWD_X = 0,  // out = -xi * Dx(in)
+  LINE_FWD_Y = 1,  // out = aux - eta * Dy(in)
+  LINE_ADJ_X = 2,  // out = Dx^T(xi * in)
+  LINE_ADJ_Y = 3   // out = aux2 - cdt * (aux + Dy^T(eta * in))
+};
+
+struct LineLaunch {
+  const void* in;
+  const void* aux;
+  const void* aux2;
+  void* out;
+  int mode;
+  int dir;          // 0: x lines (rows), 1: y lines (columns)
+  double cdt;
+};
+
+hipError_t launch_line(const Plan& p, const LineLaunch& L, hipStream_t s);
+
+struct NodeFwdLaunch {
+  const void* u;       // u^n
+  const void* T;       // advection term from the line passes
+  const void* L1;      // L^{n-1}
+  const void* L2;
+  const void* L3;
+  const void* mu_a;
+  const void* mu_s;
+  void* u_out;         // u^{n+1}
+  void* L_out;         // L^n
+  double* flux;        // [Nq][K+1][4][npos] or nullptr (replay)
+  int step;            // n (time level of u)
+};
+hipError_t launch_node_fwd(const Plan& p, const NodeFwdLaunch& L, hipStream_t s);
+
+struct NodeAdjLaunch {
+  void* v1;            // ring slot n+1 (holds ubar^{n+1}; converted in place to v^{n+1})
+  const void* v2;      // v^{n+2}
+  const void* v3;
+  const void* v4;
+  const void* u;       // u^n
+  const void* mu_a;
+  const void* mu_s;
+  const double* inj;   // [Nq][K+1][4][npos] detector injection
+  void* w_out;         // w^n
+  void* p_out;         // P1
+  double* ga;
+  double* gb;
+  int step;            // n
+  int convert_v1;      // apply P^T to the boundary nodes of v1 (0 when slot n+1 is beyond K)
+};
+hipError_t launch_node_adj(const Plan& p, const NodeAdjLaunch& L, hipStream_t s);
+
+hipError_t launch_detect(const Plan& p, const double* flux, double* G, int K, hipStream_t s);
+hipError_t launch_inject(const Plan& p, const double* Gbar, double* inj, int K, hipStream_t s);
+hipError_t launch_misfit(const Plan& p, const double* G, const double* Gm, double* Gbar, double* J,
+                         int K, hipStream_t s);
+hipError_t launch_grad_reduce(const Plan& p, const double* ga, const double* gb, double* da, double* db,
+                              hipStream_t s);
+hipError_t launch_unpermute(const Plan& p, const void* state, void* out, hipStream_t s);
+
+}  // namespace rte

@@ -1,0 +1,233 @@
+"""Python binding of librte.so (argument marshalling only).
+
+Every step of the solve runs in the library's HIP kernels; this module turns a
+problem description into the C structs, allocates outputs and the workspace
+with torch on the current CUDA (HIP) device, and passes raw pointers plus the
+current stream.  It never computes any part of the method itself and raises if
+the library is missing: there is no CPU fallback.
+
+Problem descriptions are duck-typed: any object with the fields of the C
+``rte_problem`` (xmin, xmax, ymin, ymax, Nx, Ny, M, K, dt, c, g, hg_exponent,
+n_in, n_out, fc_d, fc_C, filt_alpha, filt_beta), a list ``beams`` (x, y,
+theta, sigma_x, sigma_theta, tau, sigma_t, t0, group) and a list
+``detectors`` (x, y, sigma_d).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+from .fc_tables import fc_tables
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librte.so")
+
+RTE_OK, RTE_EINVAL, RTE_ENOMEM, RTE_EDEVICE, RTE_EUNSUPPORTED, RTE_ESTATE = 0, -1, -2, -3, -5, -6
+RTE_F64, RTE_F32 = 0, 1
+
+
+class RteError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("rte error %d: %s" % (code, msg))
+        self.code = code
+
+
+class rte_problem(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("Nx", ctypes.c_int64), ("Ny", ctypes.c_int64), ("M", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("xmin", ctypes.c_double), ("xmax", ctypes.c_double), ("ymin", ctypes.c_double),
+                ("ymax", ctypes.c_double), ("c", ctypes.c_double), ("dt", ctypes.c_double),
+                ("g", ctypes.c_double), ("hg_exponent", ctypes.c_double), ("n_in", ctypes.c_double),
+                ("n_out", ctypes.c_double), ("fc_d", ctypes.c_int64), ("fc_C", ctypes.c_int64),
+                ("filt_alpha", ctypes.c_double), ("filt_beta", ctypes.c_double),
+                ("fc_Q", ctypes.POINTER(ctypes.c_double)), ("fc_A", ctypes.POINTER(ctypes.c_double)),
+                ("ckpt_every", ctypes.c_int64)]
+
+
+class rte_beam(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("x", "y", "theta", "sigma_x", "sigma_theta", "tau", "sigma_t", "t0")] + \
+               [("group", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+
+
+class rte_detector(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_double), ("y", ctypes.c_double), ("sigma_d", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librte.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("librte.so not found at %s: run paper_2202_09421_amd.build.build() first" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+        L.rte_plan_create.argtypes = [ctypes.POINTER(rte_problem), ctypes.POINTER(rte_beam), i64,
+                                      ctypes.POINTER(rte_detector), i64, ctypes.POINTER(vp)]
+        L.rte_plan_destroy.argtypes = [vp]
+        L.rte_plan_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.rte_workspace_bytes.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64)]
+        L.rte_forward.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp, i64, vp]
+        L.rte_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.rte_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.rte_last_error.restype = ctypes.c_char_p
+        for f in ("rte_plan_create", "rte_plan_destroy", "rte_plan_info", "rte_workspace_bytes", "rte_forward",
+                  "rte_adjoint", "rte_gradient"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != RTE_OK:
+        raise RteError(rc, lib().rte_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_problem(spec, dtype=RTE_F64, ckpt_every=0):
+    """Build the C structs for a problem description (see module docstring)."""
+    Q, A = fc_tables(spec.fc_d, spec.fc_C)
+    Qc = np.ascontiguousarray(Q, dtype=np.float64)
+    Ac = np.ascontiguousarray(A, dtype=np.float64)
+    p = rte_problem()
+    p.dtype = dtype
+    p.Nx, p.Ny, p.M, p.K = spec.Nx, spec.Ny, spec.M, spec.K
+    p.xmin, p.xmax, p.ymin, p.ymax = spec.xmin, spec.xmax, spec.ymin, spec.ymax
+    p.c, p.dt, p.g, p.hg_exponent = spec.c, spec.dt, spec.g, spec.hg_exponent
+    p.n_in, p.n_out = spec.n_in, spec.n_out
+    p.fc_d, p.fc_C = spec.fc_d, spec.fc_C
+    p.filt_alpha, p.filt_beta = spec.filt_alpha, spec.filt_beta
+    p.fc_Q = Qc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.fc_A = Ac.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.ckpt_every = ckpt_every
+    beams = (rte_beam * max(1, len(spec.beams)))()
+    for k, b in enumerate(spec.beams):
+        beams[k] = rte_beam(b.x, b.y, b.theta, b.sigma_x, b.sigma_theta, b.tau, b.sigma_t, b.t0, b.group, 0)
+    dets = (rte_detector * max(1, len(spec.detectors)))()
+    for k, dd in enumerate(spec.detectors):
+        dets[k] = rte_detector(dd.x, dd.y, dd.sigma_d)
+    return p, beams, len(spec.beams), dets, len(spec.detectors), (Qc, Ac)
+
+
+class Plan:
+    """A library plan for one problem description (all Nq sources)."""
+
+    def __init__(self, spec, dtype=torch.float64, ckpt_every=0, device=None):
+        self.spec = spec
+        self.dtype = dtype
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        code = RTE_F64 if dtype == torch.float64 else RTE_F32
+        prob, beams, nb, dets, nd, self._keep = make_problem(spec, code, ckpt_every)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().rte_plan_create(ctypes.byref(prob), beams, nb, dets, nd, ctypes.byref(h)))
+        self._h = h
+        Nq, Nd, Npx, Npy = (ctypes.c_int64() for _ in range(4))
+        _check(lib().rte_plan_info(h, ctypes.byref(Nq), ctypes.byref(Nd), ctypes.byref(Npx), ctypes.byref(Npy)))
+        self.Nq, self.Nd, self.Np_x, self.Np_y = Nq.value, Nd.value, Npx.value, Npy.value
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rte_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, with_adjoint=True):
+        b = ctypes.c_int64()
+        _check(lib().rte_workspace_bytes(self._h, 1 if with_adjoint else 0, ctypes.byref(b)))
+        return b.value
+
+    def workspace(self, with_adjoint=True):
+        need = self.workspace_bytes(with_adjoint)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _medium(self, mu_a, mu_s):
+        ny, nx = self.spec.Ny + 1, self.spec.Nx + 1
+        a = torch.as_tensor(mu_a, dtype=self.dtype, device=self.device).contiguous()
+        b = torch.as_tensor(mu_s, dtype=self.dtype, device=self.device).contiguous()
+        if a.shape != (ny, nx) or b.shape != (ny, nx):
+            raise ValueError("mu_a and mu_s must have shape (Ny+1, Nx+1)")
+        return a, b
+
+    def forward(self, mu_a, mu_s, save_states=False, want_u_final=False):
+        a, b = self._medium(mu_a, mu_s)
+        G = torch.empty((self.Nq, self.Nd, self.spec.K), dtype=torch.float64, device=self.device)
+        uK = None
+        if want_u_final:
+            uK = torch.empty((self.Nq, self.spec.Ny + 1, self.spec.Nx + 1, self.spec.M), dtype=self.dtype,
+                             device=self.device)
+        ws = self.workspace(save_states)
+        _check(lib().rte_forward(self._h, _ptr(a), _ptr(b), _ptr(G), _ptr(uK), 1 if save_states else 0,
+                                 _ptr(ws), ws.numel(), _stream()))
+        self._medium_saved = (a, b)
+        return (G, uK) if want_u_final else G
+
+    def adjoint(self, G_bar, mu_a=None, mu_s=None):
+        if mu_a is None:
+            a, b = self._medium_saved
+        else:
+            a, b = self._medium(mu_a, mu_s)
+        gbar = torch.as_tensor(G_bar, dtype=torch.float64, device=self.device).contiguous()
+        ny, nx = self.spec.Ny + 1, self.spec.Nx + 1
+        da = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+        db = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+        ws = self.workspace(True)
+        _check(lib().rte_adjoint(self._h, _ptr(a), _ptr(b), _ptr(gbar), _ptr(da), _ptr(db), _ptr(ws), ws.numel(),
+                                 _stream()))
+        return da, db
+
+    def gradient(self, mu_a, mu_s, G_meas):
+        a, b = self._medium(mu_a, mu_s)
+        gm = torch.as_tensor(G_meas, dtype=torch.float64, device=self.device).contiguous()
+        ny, nx = self.spec.Ny + 1, self.spec.Nx + 1
+        J = torch.empty((1,), dtype=torch.float64, device=self.device)
+        da = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+        db = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+        G = torch.empty((self.Nq, self.Nd, self.spec.K), dtype=torch.float64, device=self.device)
+        ws = self.workspace(True)
+        _check(lib().rte_gradient(self._h, _ptr(a), _ptr(b), _ptr(gm), _ptr(J), _ptr(da), _ptr(db), _ptr(G),
+                                  _ptr(ws), ws.numel(), _stream()))
+        return J, da, db, G
+
+
+class RTEFunction(torch.autograd.Function):
+    """G = F(mu_a, mu_s): detector traces [Nq, Nd, K] of the forward solve.
+    backward runs the library's exact discrete adjoint (checkpointed replay
+    when the plan was made with ckpt_every > 0)."""
+
+    @staticmethod
+    def forward(ctx, mu_a, mu_s, plan):
+        ctx.plan = plan
+        ctx.save_for_backward(mu_a, mu_s)
+        return plan.forward(mu_a.detach(), mu_s.detach(), save_states=True)
+
+    @staticmethod
+    def backward(ctx, grad_G):
+        mu_a, mu_s = ctx.saved_tensors
+        da, db = ctx.plan.adjoint(grad_G.contiguous(), mu_a.detach(), mu_s.detach())
+        return da.to(mu_a.dtype), db.to(mu_s.dtype), None
+
+
+def detector_traces(mu_a, mu_s, plan):
+    return RTEFunction.apply(mu_a, mu_s, plan)

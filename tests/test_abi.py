@@ -1,0 +1,79 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared entry
+point, and rejects bad problem descriptions before touching the device.
+Also the library's host-side FC table builder against the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "rte.h")).read()
+    return sorted(set(re.findall(r"\b(rte_[a-z_]+)\s*\(", src)))
+
+
+def _lib():
+    from paper_2202_09421_amd import rte
+    if not os.path.exists(rte.LIB_PATH):
+        from paper_2202_09421_amd.build import build
+        build()
+    return rte.lib()
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib()
+    names = _declared()
+    assert {"rte_plan_create", "rte_forward", "rte_adjoint", "rte_gradient"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _bad_problem(**kw):
+    import workloads as W
+    from paper_2202_09421_amd import rte
+    spec = W.small_problem(N=12, M=8, K=4)
+    prob, beams, nb, dets, nd, keep = rte.make_problem(spec)
+    for k, v in kw.items():
+        setattr(prob, k, v)
+    return prob, beams, nb, dets, nd, keep
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("M", 6, "multiple of 4"),
+    ("Nx", 5, "2*fc_d"),
+    ("K", 0, "K must"),
+    ("g", 1.0, "|g|"),
+    ("dt", -1.0, "dt and c"),
+    ("dtype", 7, "dtype"),
+])
+def test_plan_create_rejects_bad_input(field, value, msg):
+    from paper_2202_09421_amd import rte
+    L = _lib()
+    prob, beams, nb, dets, nd, keep = _bad_problem(**{field: value})
+    h = ctypes.c_void_p()
+    rc = L.rte_plan_create(ctypes.byref(prob), beams, nb, dets, nd, ctypes.byref(h))
+    assert rc == rte.RTE_EINVAL
+    assert msg in L.rte_last_error().decode()
+    assert not h.value
+
+
+def test_null_arguments_are_errors():
+    from paper_2202_09421_amd import rte
+    L = _lib()
+    assert L.rte_plan_create(None, None, 0, None, 0, None) == rte.RTE_EINVAL
+    assert L.rte_forward(None, None, None, None, None, 0, None, 0, None) == rte.RTE_EINVAL
+    assert "NULL" in L.rte_last_error().decode()
+    assert L.rte_adjoint(None, None, None, None, None, None, None, 0, None) == rte.RTE_EINVAL
+
+
+def test_library_fc_tables_match_oracle():
+    from oracle.fc_gram import blend_table
+    from paper_2202_09421_amd.fc_tables import fc_tables
+    Q, A = fc_tables(5, 25)
+    Qo, Ao = blend_table(5, 25)
+    assert np.allclose(Q, Qo, rtol=0, atol=1e-15)
+    assert np.allclose(A, Ao, rtol=1e-14, atol=1e-14 * np.abs(Ao).max())
