@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark of the FC-DOM forward + adjoint gradient on one MI355X.
+
+One benchmark step = one full gradient evaluation of the FP64 gradient
+workload (4 x 4 cm, 257 x 257 nodes, 32 ordinates, HG g = 0.9, Fresnel
+n = 1.4, background mu_a = 0.2 / mu_s = 50 per cm, 1 beam, 32 detectors,
+2000 AB4 steps): forward solve with every state kept, misfit against
+synthetic measurements (forward solve on the medium with three inclusions,
+10 % multiplicative noise), exact discrete adjoint, dJ/dmu_a and dJ/dmu_s.
+
+value = cells * ordinates * time steps * sources / seconds per gradient
+(a unit is one node x one ordinate x one step, counted once for the whole
+forward + adjoint pair).  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (last line of stdout).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+WORD = {"f64": 8, "f32": 4}
+
+# compulsory words moved per unit (node x ordinate) by one launch of each kernel class
+KERNEL_WORDS = {
+    "line_x_fwd": 2,   # read u, write -xi Dx u
+    "line_y_fwd": 3,   # read u and the x term, write the advection term
+    "node_fwd": 7,     # read u, T, L^{n-1..n-3}; write u^{n+1}, L^n
+    "node_adj": 7,     # read v^{n+1..n+4}, u^n; write w, P1
+    "line_x_adj": 2,   # read w, write Dx^T(xi w)
+    "line_y_adj": 4,   # read w, the x term, P1; write ubar^n
+}
+PATH_WORDS_STORE_ALL = 12  # algorithmic fwd + adj per unit: 6 + 6 words
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(spec, target_s=15.0):
+    """Time the FP64 oracle (single thread) on the first steps of the same
+    workload: forward + adjoint gradient on the full grid."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.solver import Oracle
+
+    with threadpool_limits(limits=1):
+        o = Oracle(spec.with_(K=2))
+        t0 = time.perf_counter()
+        o.gradient(np.zeros((1, len(spec.detectors), 2)))
+        per_step = (time.perf_counter() - t0) / 2
+        Ks = int(max(4, min(60, target_s / max(per_step, 1e-3))))
+        sample = spec.with_(K=Ks)
+        o = Oracle(sample)
+        t0 = time.perf_counter()
+        o.gradient(np.zeros((1, len(spec.detectors), Ks)))
+        dt = time.perf_counter() - t0
+    units = (spec.Nx + 1) * (spec.Ny + 1) * spec.M * Ks * spec.Nq
+    return {"value": units / dt, "unit": "cell*ordinate*steps/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d steps of the same workload (full 257x257 grid, 32 ordinates), "
+                      "forward + adjoint gradient, NumPy FP64, 1 thread, %.1f s" % (Ks, spec.K, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
+              "(the multi-GPU sharding is a design, not part of this build).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2202_09421_amd import rte
+
+    torch.cuda.set_device(0)
+    spec = W.config(1)
+    tdt = torch.float64 if args.dtype == "f64" else torch.float32
+    plan = rte.Plan(spec, tdt)
+    ny, nx = spec.Ny + 1, spec.Nx + 1
+    a_true = torch.tensor(spec.mu_a, device="cuda", dtype=tdt)
+    b_true = torch.tensor(spec.mu_s, device="cuda", dtype=tdt)
+    a_bg = torch.full((ny, nx), 0.2, device="cuda", dtype=tdt)
+    b_bg = torch.full((ny, nx), 50.0, device="cuda", dtype=tdt)
+    log("bench: %s, workspace %.1f GB" % (spec.name, plan.workspace_bytes(True) / 1e9))
+    G_true = plan.forward(a_true, b_true)
+    noise = torch.tensor(W.measured_noise(1, tuple(G_true.shape)), device="cuda")
+    Gm = (G_true * noise).contiguous()
+    torch.cuda.synchronize()
+
+    for k in range(args.warmup):
+        plan.gradient(a_bg, b_bg, Gm)
+        torch.cuda.synchronize()
+        log("bench: warmup %d done" % k)
+
+    rte.profile_enable(plan, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        J, ga, gb, G = plan.gradient(a_bg, b_bg, Gm)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = rte.profile_read(plan)
+    rte.profile_enable(plan, False)
+    log("bench: timed %d gradients in %.3f s (J = %.6e)" % (args.steps, elapsed, float(J.item())))
+    if not np.isfinite(float(J.item())) or not torch.isfinite(ga).all():
+        raise RuntimeError("non-finite gradient")
+
+    units_per_grad = nx * ny * spec.M * spec.K * spec.Nq
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = units_per_grad * args.steps / elapsed
+
+    word = WORD[args.dtype]
+    units_per_launch = nx * ny * spec.M * spec.Nq
+    kernels = {}
+    for cls, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        avg_us = 1000.0 * ms / cnt
+        gbs = KERNEL_WORDS[cls] * word * units_per_launch / (avg_us * 1e-6) / 1e9
+        kernels[cls] = {"avg_us": round(avg_us, 2), "launches": cnt, "GB_s": round(gbs, 1),
+                        "share": round(ms / max(1e-9, sum(v[0] for v in prof.values())), 3)}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+    ach = kernels[dom]["GB_s"]
+    path_gbs = value * PATH_WORDS_STORE_ALL * word / 1e9
+    out = {
+        "metric": "cell*ordinate*steps/s fwd+adjoint on 1 GPU, batched vs plain, at rel-L2 1e-10",
+        "value": value,
+        "unit": "cell*ordinate*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": spec.name, "grid": "%dx%d" % (nx, ny), "ordinates": spec.M, "time_steps": spec.K,
+                   "sources": spec.Nq, "detectors": len(spec.detectors), "states": "all kept (no replay)",
+                   "path": "plain (one source: batched == plain)"},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "traffic": None, "kernel": dom,
+                     "bytes_per_launch": KERNEL_WORDS[dom] * word * units_per_launch},
+        "path_roofline": {"algorithmic_bytes_per_unit": PATH_WORDS_STORE_ALL * word, "achieved_GB_s": path_gbs,
+                          "frac": path_gbs / HBM_PEAK_GBS},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -140,6 +140,28 @@ int rte_gradient(rte_plan* plan, const void* mu_a, const void* mu_s, const doubl
                  double* J, double* dmu_a, double* dmu_s, double* G, void* workspace,
                  int64_t workspace_bytes, void* stream);
 
+/* Instrumentation.  Kernel classes of one time step: */
+typedef enum {
+  RTE_K_LINE_X_FWD = 0, /* x-line FC derivative                       */
+  RTE_K_LINE_Y_FWD = 1, /* y-line FC derivative                       */
+  RTE_K_NODE_FWD = 2,   /* scattering, AB4, inflow condition, flux    */
+  RTE_K_NODE_ADJ = 3,   /* adjoint node pass and gradient accumulation */
+  RTE_K_LINE_X_ADJ = 4, /* x-line transposed derivative               */
+  RTE_K_LINE_Y_ADJ = 5, /* y-line transposed derivative + combination */
+  RTE_K_COUNT = 6
+} rte_kernel_class;
+
+/* enable != 0: every later launch of a time-step kernel on this plan is
+ * bracketed by two hipEvents recorded on the call's stream (they add a few
+ * microseconds per launch).  enable == 0 stops recording and drops pending
+ * records.                                                                 */
+int rte_profile_enable(rte_plan* plan, int enable);
+
+/* Waits for the recorded events and returns, per kernel class, the summed
+ * GPU time (ms) and the number of launches since the last read; then clears
+ * the records.  total_ms and launches point to RTE_K_COUNT entries (host). */
+int rte_profile_read(rte_plan* plan, double* total_ms, int64_t* launches);
+
 /* Thread-local message of the last failed call ("" if none). */
 const char* rte_last_error(void);
 

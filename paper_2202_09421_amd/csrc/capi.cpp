@@ -34,12 +34,20 @@ struct Ctx {
 
 inline void* at(void* base, int64_t k, int64_t S) { return static_cast<char*>(base) + k * S; }
 
+#define TIMED(cls, expr)                          \
+  do {                                            \
+    hipEvent_t stop_;                             \
+    RTE_CHECK(prof_begin(c.p, (cls), c.st, &stop_)); \
+    RTE_CHECK(expr);                              \
+    RTE_CHECK(prof_end(stop_, c.st));             \
+  } while (0)
+
 // One forward step u^n -> u^{n+1}: x lines, y lines, node update.
 int fwd_step(Ctx& c, int n, const void* un, void* unp1, double* flux) {
   LineLaunch lx{un, nullptr, nullptr, c.ws.tx, LINE_FWD_X, 0, 0.0};
-  RTE_CHECK(launch_line(c.p, lx, c.st));
+  TIMED(RTE_K_LINE_X_FWD, launch_line(c.p, lx, c.st));
   LineLaunch ly{un, c.ws.tx, nullptr, c.ws.tt, LINE_FWD_Y, 1, 0.0};
-  RTE_CHECK(launch_line(c.p, ly, c.st));
+  TIMED(RTE_K_LINE_Y_FWD, launch_line(c.p, ly, c.st));
   NodeFwdLaunch nf;
   nf.u = un;
   nf.T = c.ws.tt;
@@ -52,7 +60,7 @@ int fwd_step(Ctx& c, int n, const void* un, void* unp1, double* flux) {
   nf.L_out = c.ws.lring[n % 3];
   nf.flux = flux;
   nf.step = n;
-  RTE_CHECK(launch_node_fwd(c.p, nf, c.st));
+  TIMED(RTE_K_NODE_FWD, launch_node_fwd(c.p, nf, c.st));
   return RTE_OK;
 }
 
@@ -74,11 +82,11 @@ int adj_step(Ctx& c, int n, const void* un) {
   na.gb = c.ws.gb;
   na.step = n;
   na.convert_v1 = (n + 1 <= c.p.K) ? 1 : 0;
-  RTE_CHECK(launch_node_adj(c.p, na, c.st));
+  TIMED(RTE_K_NODE_ADJ, launch_node_adj(c.p, na, c.st));
   LineLaunch lx{c.ws.wbuf, nullptr, nullptr, c.ws.tx, LINE_ADJ_X, 0, cdt};
-  RTE_CHECK(launch_line(c.p, lx, c.st));
+  TIMED(RTE_K_LINE_X_ADJ, launch_line(c.p, lx, c.st));
   LineLaunch ly{c.ws.wbuf, c.ws.tx, c.ws.tt, c.ws.vring[n % 4], LINE_ADJ_Y, 1, cdt};
-  RTE_CHECK(launch_line(c.p, ly, c.st));
+  TIMED(RTE_K_LINE_Y_ADJ, launch_line(c.p, ly, c.st));
   return RTE_OK;
 }
 
@@ -263,6 +271,43 @@ int rte_gradient(rte_plan* h, const void* mu_a, const void* mu_s, const double* 
     set_error(e.what());
     return RTE_EINVAL;
   }
+}
+
+int rte_profile_enable(rte_plan* h, int enable) {
+  if (!nonnull(h, "plan")) return RTE_EINVAL;
+  Plan& p = *reinterpret_cast<Plan*>(h);
+  p.prof = enable != 0;
+  if (!p.prof)
+    for (int c = 0; c < RTE_K_COUNT; ++c) {
+      for (auto& e : p.ev_rec[c]) {
+        p.ev_pool.push_back(e.first);
+        p.ev_pool.push_back(e.second);
+      }
+      p.ev_rec[c].clear();
+    }
+  return RTE_OK;
+}
+
+int rte_profile_read(rte_plan* h, double* total_ms, int64_t* launches) {
+  if (!nonnull(h, "plan") || !nonnull(total_ms, "total_ms") || !nonnull(launches, "launches")) return RTE_EINVAL;
+  Plan& p = *reinterpret_cast<Plan*>(h);
+  for (int c = 0; c < RTE_K_COUNT; ++c) {
+    double tot = 0.0;
+    for (auto& e : p.ev_rec[c]) {
+      RTE_CHECK(hipEventSynchronize(e.second));
+      float ms = 0.f;
+      RTE_CHECK(hipEventElapsedTime(&ms, e.first, e.second));
+      tot += ms;
+    }
+    total_ms[c] = tot;
+    launches[c] = (int64_t)p.ev_rec[c].size();
+    for (auto& e : p.ev_rec[c]) {
+      p.ev_pool.push_back(e.first);
+      p.ev_pool.push_back(e.second);
+    }
+    p.ev_rec[c].clear();
+  }
+  return RTE_OK;
 }
 
 const char* rte_last_error(void) { return last_error(); }

@@ -426,9 +426,39 @@ int plan_destroy(rte_plan* h) {
   if (!h) return RTE_OK;
   Plan* p = reinterpret_cast<Plan*>(h);
   free_tables(p->dev);
+  for (int c = 0; c < RTE_K_COUNT; ++c)
+    for (auto& e : p->ev_rec[c]) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   delete p;
   return RTE_OK;
 }
+
+static hipError_t take_event(Plan& p, hipEvent_t* e) {
+  if (!p.ev_pool.empty()) {
+    *e = p.ev_pool.back();
+    p.ev_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+hipError_t prof_begin(Plan& p, int cls, hipStream_t s, hipEvent_t* stop) {
+  *stop = nullptr;
+  if (!p.prof) return hipSuccess;
+  hipEvent_t a, b;
+  hipError_t e = take_event(p, &a);
+  if (e != hipSuccess) return e;
+  e = take_event(p, &b);
+  if (e != hipSuccess) return e;
+  p.ev_rec[cls].push_back({a, b});
+  *stop = b;
+  return hipEventRecord(a, s);
+}
+
+hipError_t prof_end(hipEvent_t stop, hipStream_t s) { return stop ? hipEventRecord(stop, s) : hipSuccess; }
 
 // ---------------------------------------------------------------- workspace
 int64_t state_elems(const Plan& p) { return p.Nq * p.M * p.nx * p.ny; }

@@ -85,7 +85,15 @@ struct Plan {
   int64_t ckpt_every = 0;
   bool have_forward = false;   // a saved forward lives in the workspace
   int64_t saved_K = 0;
+  // instrumentation: event pairs per kernel class
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec[RTE_K_COUNT];
 };
+
+// Bracket a launch with profiling events when enabled.
+hipError_t prof_begin(Plan& p, int cls, hipStream_t s, hipEvent_t* stop);
+hipError_t prof_end(hipEvent_t stop, hipStream_t s);
 
 // ---------------------------------------------------------------- workspace map
 struct Workspace {

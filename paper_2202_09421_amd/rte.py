@@ -75,9 +75,11 @@ def lib():
         L.rte_forward.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp, i64, vp]
         L.rte_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp]
         L.rte_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.rte_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.rte_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.rte_last_error.restype = ctypes.c_char_p
         for f in ("rte_plan_create", "rte_plan_destroy", "rte_plan_info", "rte_workspace_bytes", "rte_forward",
-                  "rte_adjoint", "rte_gradient"):
+                  "rte_adjoint", "rte_gradient", "rte_profile_enable", "rte_profile_read"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -209,6 +211,22 @@ class Plan:
         _check(lib().rte_gradient(self._h, _ptr(a), _ptr(b), _ptr(gm), _ptr(J), _ptr(da), _ptr(db), _ptr(G),
                                   _ptr(ws), ws.numel(), _stream()))
         return J, da, db, G
+
+
+KERNEL_CLASSES = ("line_x_fwd", "line_y_fwd", "node_fwd", "node_adj", "line_x_adj", "line_y_adj")
+
+
+def profile_enable(plan, on=True):
+    _check(lib().rte_profile_enable(plan._h, 1 if on else 0))
+
+
+def profile_read(plan):
+    """{class: (total_ms, launches)} since the last read (waits for the GPU)."""
+    n = len(KERNEL_CLASSES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(lib().rte_profile_read(plan._h, ms, cnt))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES)}
 
 
 class RTEFunction(torch.autograd.Function):
