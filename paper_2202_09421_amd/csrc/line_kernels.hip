@@ -270,6 +270,8 @@ static hipError_t launch_t(const Plan& p, const LineLaunch& L, hipStream_t s) {
 }
 
 hipError_t launch_line(const Plan& p, const LineLaunch& L, hipStream_t s) {
+  const FcPlanDev& fc = (L.dir == 0) ? p.fcx : p.fcy;
+  if (fc.n1 > 0) return launch_line4(p, L, s);
   if (p.dtype == RTE_F64) return launch_t<double>(p, L, s);
   return launch_t<float>(p, L, s);
 }

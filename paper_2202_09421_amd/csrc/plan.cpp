@@ -152,6 +152,14 @@ static bool build_fc(const rte_problem& pb, int n, double h, std::vector<double>
   for (int i = 0; i < d * d; ++i) buf.push_back(pb.fc_Q[i]);
   offs.push_back(buf.size());
   for (int i = 0; i < C * d; ++i) buf.push_back(pb.fc_A[i]);
+  // roots of unity for the four-step kernel
+  offs.push_back(buf.size());
+  for (int e = 0; e < Np; ++e) {
+    const double ang = -2.0 * kPi * (double)e / (double)Np;
+    buf.push_back(std::cos(ang));
+    buf.push_back(std::sin(ang));
+  }
+  if (!fourstep_split(Np, &fc.n1, &fc.n2)) fc.n1 = fc.n2 = 0;
   return true;
 }
 
@@ -416,8 +424,8 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
     return RTE_EDEVICE;
   }
   const double* fb = p.dev.fc_buf;
-  p.fcx.tw = fb + ox[0]; p.fcx.mu = fb + ox[1]; p.fcx.Q = fb + ox[2]; p.fcx.A = fb + ox[3];
-  p.fcy.tw = fb + oy[0]; p.fcy.mu = fb + oy[1]; p.fcy.Q = fb + oy[2]; p.fcy.A = fb + oy[3];
+  p.fcx.tw = fb + ox[0]; p.fcx.mu = fb + ox[1]; p.fcx.Q = fb + ox[2]; p.fcx.A = fb + ox[3]; p.fcx.roots = fb + ox[4];
+  p.fcy.tw = fb + oy[0]; p.fcy.mu = fb + oy[1]; p.fcy.Q = fb + oy[2]; p.fcy.A = fb + oy[3]; p.fcy.roots = fb + oy[4];
   *out = reinterpret_cast<rte_plan*>(P);
   return RTE_OK;
 }

@@ -37,7 +37,12 @@ struct FcPlanDev {
   const double* mu;         // Np real multipliers: derivative factor * filter / Np
   const double* Q;          // d*d
   const double* A;          // C*d
+  int n1, n2;               // four-step split Np = n1 * n2 (0: generic Stockham kernel)
+  const double* roots;      // Np complex roots exp(-2 pi i e / Np), interleaved
 };
+
+// Four-step splits with register codelets (Np -> n1 x n2); 0 if none.
+bool fourstep_split(int Np, int* n1, int* n2);
 
 // Per-slot boundary rule for one node type (9 types: interior, 4 edges, 4 corners).
 struct BcRule {
@@ -138,6 +143,7 @@ struct LineLaunch {
 };
 
 hipError_t launch_line(const Plan& p, const LineLaunch& L, hipStream_t s);
+hipError_t launch_line4(const Plan& p, const LineLaunch& L, hipStream_t s);
 
 struct NodeFwdLaunch {
   const void* u;       // u^n
