@@ -89,6 +89,37 @@ __device__ __forceinline__ void scatter_mfma(const T* X, T* S, int LS, const dou
   }
 }
 
+// One node's four slots of one ordinate group: 32 bytes (FP64) or 16 (FP32),
+// aligned, moved with vector loads.
+template <typename T>
+struct Quad {
+  T v[4];
+};
+
+template <typename T>
+__device__ __forceinline__ Quad<T> ldq(const T* p) {
+  Quad<T> q;
+  if constexpr (sizeof(T) == 8) {
+    const double2 x = reinterpret_cast<const double2*>(p)[0];
+    const double2 y = reinterpret_cast<const double2*>(p)[1];
+    q.v[0] = x.x; q.v[1] = x.y; q.v[2] = y.x; q.v[3] = y.y;
+  } else {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    q.v[0] = x.x; q.v[1] = x.y; q.v[2] = x.z; q.v[3] = x.w;
+  }
+  return q;
+}
+
+template <typename T>
+__device__ __forceinline__ void stq(T* p, const Quad<T>& q) {
+  if constexpr (sizeof(T) == 8) {
+    reinterpret_cast<double2*>(p)[0] = make_double2(q.v[0], q.v[1]);
+    reinterpret_cast<double2*>(p)[1] = make_double2(q.v[2], q.v[3]);
+  } else {
+    *reinterpret_cast<float4*>(p) = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
+  }
+}
+
 // ---------------------------------------------------------------- forward
 template <typename T>
 struct NodeFwdArgs {
@@ -102,7 +133,12 @@ struct NodeFwdArgs {
   double cdt;
 };
 
-template <typename T, int TN>
+// Thread layout: quad index qd = g * TN + nd (group-major, so a wave reads
+// contiguous 2 KB runs); each thread owns QPT quads.  All global loads of a
+// step are issued before the first barrier and stay in registers, so their
+// latency overlaps the MFMA phase.  (L_out aliases L3 by design: every quad
+// is read before it is written, by the same thread.)
+template <typename T, int TN, int QPT>
 __global__ __launch_bounds__(kNodeThreads) void node_fwd_kernel(NodeFwdArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const NodeGeom& G = a.geo;
@@ -116,13 +152,32 @@ __global__ __launch_bounds__(kNodeThreads) void node_fwd_kernel(NodeFwdArgs<T> a
   const int Nn = G.nx * G.ny;
   const int node0 = blockIdx.x * TN;
   const int64_t ib = (int64_t)q * G.inst_stride;
-  const int nel = G.G * TN * kGroup;
+  const int nq = G.G * TN;
 
-  // 1. stage u^n, a, b
-  for (int e = tid; e < nel; e += kNodeThreads) {
-    const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
+  Quad<T> tq[QPT], l1[QPT], l2[QPT], l3[QPT];
+  int gq[QPT], nq_[QPT];
+  bool ok[QPT];
+#pragma unroll
+  for (int k = 0; k < QPT; ++k) {
+    const int qd = tid + k * kNodeThreads;
+    const int g = qd / TN, nd = qd - g * TN;
     const int gn = node0 + nd;
-    Us[nd * LS + g * kGroup + r] = (gn < Nn) ? a.u[ib + g * G.grp_stride + (int64_t)gn * kGroup + r] : T(0);
+    gq[k] = g;
+    nq_[k] = nd;
+    ok[k] = (qd < nq) && (gn < Nn);
+    Quad<T> u = {{T(0), T(0), T(0), T(0)}};
+    if (ok[k]) {
+      const int64_t off = ib + g * G.grp_stride + (int64_t)gn * kGroup;
+      u = ldq(a.u + off);
+      tq[k] = ldq(a.Tt + off);
+      l1[k] = ldq(a.L1 + off);
+      l2[k] = ldq(a.L2 + off);
+      l3[k] = ldq(a.L3 + off);
+    }
+    if (qd < nq) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Us[nd * LS + g * kGroup + r] = u.v[r];
+    }
   }
   for (int e = tid; e < TN * (G.Mpad - G.M); e += kNodeThreads) {
     const int nd = e / (G.Mpad - G.M), s = G.M + e % (G.Mpad - G.M);
@@ -135,52 +190,62 @@ __global__ __launch_bounds__(kNodeThreads) void node_fwd_kernel(NodeFwdArgs<T> a
   }
   __syncthreads();
 
-  // 2. scattering on MFMA
   scatter_mfma<T, TN>(Us, Ss, LS, a.Wt, G.Mpad);
   __syncthreads();
 
-  // 3. L^n and the AB4 combination
+  // L^n and the AB4 combination
   const T cdt = T(a.cdt);
-  for (int e = tid; e < nel; e += kNodeThreads) {
-    const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
-    const int gn = node0 + nd;
-    if (gn >= Nn) continue;
-    const int s = g * kGroup + r;
-    const int64_t off = ib + g * G.grp_stride + (int64_t)gn * kGroup + r;
-    const T uu = Us[nd * LS + s];
-    const T Ln = Bs[nd] * Ss[nd * LS + s] - (As[nd] + Bs[nd]) * uu + a.Tt[off];
-    const T l1 = a.L1[off], l2 = a.L2[off], l3 = a.L3[off];
-    const T ut = uu + cdt * (T(kChi0) * Ln + T(kChi1) * l1 + T(kChi2) * l2 + T(kChi3) * l3);
-    a.L_out[off] = Ln;
-    Ss[nd * LS + s] = ut;
+#pragma unroll
+  for (int k = 0; k < QPT; ++k) {
+    if (!ok[k]) continue;
+    const int g = gq[k], nd = nq_[k], gn = node0 + nd;
+    const T A = As[nd], B = Bs[nd];
+    Quad<T> Lq;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int s = g * kGroup + r;
+      const T uu = Us[nd * LS + s];
+      const T Ln = B * Ss[nd * LS + s] - (A + B) * uu + tq[k].v[r];
+      Lq.v[r] = Ln;
+      Ss[nd * LS + s] = uu + cdt * (T(kChi0) * Ln + T(kChi1) * l1[k].v[r] + T(kChi2) * l2[k].v[r] + T(kChi3) * l3[k].v[r]);
+    }
+    stq(a.L_out + ib + g * G.grp_stride + (int64_t)gn * kGroup, Lq);
   }
   __syncthreads();
 
-  // 4. inflow condition with Fresnel reflection and the beams at t_{n+1}
-  for (int e = tid; e < nel; e += kNodeThreads) {
-    const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
-    const int gn = node0 + nd;
-    if (gn >= Nn) continue;
-    const int s = g * kGroup + r;
+  // inflow condition with Fresnel reflection and the beams at t_{n+1}
+#pragma unroll
+  for (int k = 0; k < QPT; ++k) {
+    if (!ok[k]) continue;
+    const int g = gq[k], nd = nq_[k], gn = node0 + nd;
     const int j = gn / G.nx, i = gn - j * G.nx;
     const int ty = node_type(j, i, G.nx, G.ny);
-    T val = Ss[nd * LS + s];
-    if (ty != 0) {
-      const BcRule br = a.bc[ty * G.M + s];
-      if (br.flag) {
-        val = T(br.coef_a) * Ss[nd * LS + br.src_a] + T(br.coef_b) * Ss[nd * LS + br.src_b];
-        const int bp = boundary_pos(j, i, G.nx, G.ny);
-        for (int k = a.beam_off[q]; k < a.beam_off[q + 1]; ++k)
-          val += T(a.beam_sp[(int64_t)k * G.nb + bp] * a.beam_an[k * G.M + s]) * T(a.beam_tt[(int64_t)k * G.K1 + a.step + 1]);
+    Quad<T> o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int s = g * kGroup + r;
+      T val = Ss[nd * LS + s];
+      if (ty != 0) {
+        const BcRule br = a.bc[ty * G.M + s];
+        if (br.flag) {
+          val = T(br.coef_a) * Ss[nd * LS + br.src_a] + T(br.coef_b) * Ss[nd * LS + br.src_b];
+          const int bp = boundary_pos(j, i, G.nx, G.ny);
+          for (int b = a.beam_off[q]; b < a.beam_off[q + 1]; ++b)
+            val += T(a.beam_sp[(int64_t)b * G.nb + bp] * a.beam_an[b * G.M + s]) * T(a.beam_tt[(int64_t)b * G.K1 + a.step + 1]);
+        }
       }
+      o.v[r] = val;
     }
-    a.u_out[ib + g * G.grp_stride + (int64_t)gn * kGroup + r] = val;
-    Us[nd * LS + s] = val;
+    stq(a.u_out + ib + g * G.grp_stride + (int64_t)gn * kGroup, o);
+    if (a.flux) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Us[nd * LS + g * kGroup + r] = o.v[r];
+    }
   }
   if (a.flux == nullptr) return;
   __syncthreads();
 
-  // 5. detector flux on boundary nodes (FP64 accumulation)
+  // detector flux on boundary nodes (FP64 accumulation)
   for (int nd = tid; nd < TN; nd += kNodeThreads) {
     const int gn = node0 + nd;
     if (gn >= Nn) continue;
@@ -213,7 +278,7 @@ struct NodeAdjArgs {
   double cdt;
 };
 
-template <typename T, int TN>
+template <typename T, int TN, int QPT>
 __global__ __launch_bounds__(kNodeThreads) void node_adj_kernel(NodeAdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const NodeGeom& G = a.geo;
@@ -223,66 +288,46 @@ __global__ __launch_bounds__(kNodeThreads) void node_adj_kernel(NodeAdjArgs<T> a
   T* Sb = Wb + TN * LS;
   T* As = Sb + TN * LS;
   T* Bs = As + TN;
+  // [TN][G] gradient partials, 8-byte aligned after the T arrays
+  double* Pa = reinterpret_cast<double*>(smem_raw + ((sizeof(T) * (size_t)(3 * TN * LS + 2 * TN) + 7) & ~size_t(7)));
+  double* Pb = Pa + TN * G.G;
   const int tid = threadIdx.x;
   const int q = blockIdx.y;
   const int Nn = G.nx * G.ny;
   const int node0 = blockIdx.x * TN;
   const int64_t ib = (int64_t)q * G.inst_stride;
-  const int nel = G.G * TN * kGroup;
+  const int nq = G.G * TN;
 
-  for (int e = tid; e < nel; e += kNodeThreads) {
-    const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
+  Quad<T> v1[QPT], v2[QPT], v3[QPT], v4[QPT], uq[QPT];
+  int gq[QPT], ndq[QPT];
+  bool ok[QPT];
+#pragma unroll
+  for (int k = 0; k < QPT; ++k) {
+    const int qd = tid + k * kNodeThreads;
+    const int g = qd / TN, nd = qd - g * TN;
     const int gn = node0 + nd;
-    Vb[nd * LS + g * kGroup + r] = (gn < Nn) ? a.v1[ib + g * G.grp_stride + (int64_t)gn * kGroup + r] : T(0);
+    gq[k] = g;
+    ndq[k] = nd;
+    ok[k] = (qd < nq) && (gn < Nn);
+    Quad<T> z = {{T(0), T(0), T(0), T(0)}};
+    v1[k] = z;
+    if (ok[k]) {
+      const int64_t off = ib + g * G.grp_stride + (int64_t)gn * kGroup;
+      v1[k] = ldq(a.v1 + off);
+      v2[k] = ldq(a.v2 + off);
+      v3[k] = ldq(a.v3 + off);
+      v4[k] = ldq(a.v4 + off);
+      uq[k] = ldq(a.u + off);
+    }
+    if (qd < nq) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Vb[nd * LS + g * kGroup + r] = v1[k].v[r];
+    }
   }
   for (int nd = tid; nd < TN; nd += kNodeThreads) {
     const int gn = node0 + nd;
     As[nd] = (gn < Nn) ? a.mu_a[gn] : T(0);
     Bs[nd] = (gn < Nn) ? a.mu_s[gn] : T(0);
-  }
-  __syncthreads();
-
-  // 1. v^{n+1} = P^T ubar^{n+1} on boundary nodes (in place)
-  if (a.convert_v1) {
-    for (int e = tid; e < nel; e += kNodeThreads) {
-      const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
-      const int gn = node0 + nd;
-      if (gn >= Nn) continue;
-      const int s = g * kGroup + r;
-      const int j = gn / G.nx, i = gn - j * G.nx;
-      const int ty = node_type(j, i, G.nx, G.ny);
-      if (ty == 0) continue;
-      const BcRuleT rt = a.bct[ty * G.M + s];
-      T val = rt.is_target ? T(0) : Vb[nd * LS + s];
-      for (int t = 0; t < rt.ntgt; ++t) val += T(rt.coef[t]) * Vb[nd * LS + rt.tgt[t]];
-      Sb[nd * LS + s] = val;
-    }
-    __syncthreads();
-    for (int e = tid; e < nel; e += kNodeThreads) {
-      const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
-      const int gn = node0 + nd;
-      if (gn >= Nn) continue;
-      const int j = gn / G.nx, i = gn - j * G.nx;
-      if (node_type(j, i, G.nx, G.ny) == 0) continue;
-      const int s = g * kGroup + r;
-      const T val = Sb[nd * LS + s];
-      Vb[nd * LS + s] = val;
-      a.v1[ib + g * G.grp_stride + (int64_t)gn * kGroup + r] = val;
-    }
-    __syncthreads();
-  }
-
-  // 2. w^n
-  for (int e = tid; e < nel; e += kNodeThreads) {
-    const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
-    const int gn = node0 + nd;
-    const int s = g * kGroup + r;
-    T w = T(0);
-    if (gn < Nn) {
-      const int64_t off = ib + g * G.grp_stride + (int64_t)gn * kGroup + r;
-      w = T(kChi0) * Vb[nd * LS + s] + T(kChi1) * a.v2[off] + T(kChi2) * a.v3[off] + T(kChi3) * a.v4[off];
-    }
-    Wb[nd * LS + s] = w;
   }
   for (int e = tid; e < TN * (G.Mpad - G.M); e += kNodeThreads) {
     const int nd = e / (G.Mpad - G.M), s = G.M + e % (G.Mpad - G.M);
@@ -290,44 +335,82 @@ __global__ __launch_bounds__(kNodeThreads) void node_adj_kernel(NodeAdjArgs<T> a
   }
   __syncthreads();
 
-  // 3. W w on MFMA (W is symmetric)
-  scatter_mfma<T, TN>(Wb, Sb, LS, a.Wt, G.Mpad);
-  __syncthreads();
-
-  // 4. P1, w and the gradient products
-  const T cdt = T(a.cdt);
-  for (int e = tid; e < nel; e += kNodeThreads) {
-    const int g = e / (TN * kGroup), rem = e - g * TN * kGroup, nd = rem >> 2, r = rem & 3;
-    const int gn = node0 + nd;
-    if (gn >= Nn) continue;
-    const int s = g * kGroup + r;
-    const int64_t off = ib + g * G.grp_stride + (int64_t)gn * kGroup + r;
-    const T w = Wb[nd * LS + s], S = Sb[nd * LS + s];
-    T p1 = Vb[nd * LS + s] + cdt * (Bs[nd] * S - (As[nd] + Bs[nd]) * w);
-    const int j = gn / G.nx, i = gn - j * G.nx;
-    if (node_type(j, i, G.nx, G.ny) != 0) {
-      // detector misfit enters through the outgoing boundary entries
-      if (i == 0) p1 += T(a.kappa[0 * G.M + s] * a.inj[(((int64_t)q * G.K1 + a.step) * 4 + 0) * G.npos + j]);
-      if (i == G.nx - 1) p1 += T(a.kappa[1 * G.M + s] * a.inj[(((int64_t)q * G.K1 + a.step) * 4 + 1) * G.npos + j]);
-      if (j == 0) p1 += T(a.kappa[2 * G.M + s] * a.inj[(((int64_t)q * G.K1 + a.step) * 4 + 2) * G.npos + i]);
-      if (j == G.ny - 1) p1 += T(a.kappa[3 * G.M + s] * a.inj[(((int64_t)q * G.K1 + a.step) * 4 + 3) * G.npos + i]);
+  // v^{n+1} = P^T ubar^{n+1} on boundary nodes, w^n in registers and LDS
+#pragma unroll
+  for (int k = 0; k < QPT; ++k) {
+    if (!ok[k]) continue;
+    const int g = gq[k], nd = ndq[k], gn = node0 + nd;
+    if (a.convert_v1) {
+      const int j = gn / G.nx, i = gn - j * G.nx;
+      const int ty = node_type(j, i, G.nx, G.ny);
+      if (ty != 0) {
+        Quad<T> c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const BcRuleT rt = a.bct[ty * G.M + g * kGroup + r];
+          T val = rt.is_target ? T(0) : v1[k].v[r];
+          for (int t = 0; t < rt.ntgt; ++t) val += T(rt.coef[t]) * Vb[nd * LS + rt.tgt[t]];
+          c.v[r] = val;
+        }
+        v1[k] = c;
+        stq(a.v1 + ib + g * G.grp_stride + (int64_t)gn * kGroup, c);
+      }
     }
-    a.p_out[off] = p1;
-    a.w_out[off] = w;
-    const T un = a.u[off];
-    Vb[nd * LS + s] = un * w;
-    Sb[nd * LS + s] = un * (S - w);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      Wb[nd * LS + g * kGroup + r] =
+          T(kChi0) * v1[k].v[r] + T(kChi1) * v2[k].v[r] + T(kChi2) * v3[k].v[r] + T(kChi3) * v4[k].v[r];
   }
   __syncthreads();
 
-  // 5. per-node gradient sums (fixed order: deterministic)
+  scatter_mfma<T, TN>(Wb, Sb, LS, a.Wt, G.Mpad);
+  __syncthreads();
+
+  // P1, w and the gradient products
+  const T cdt = T(a.cdt);
+#pragma unroll
+  for (int k = 0; k < QPT; ++k) {
+    if (!ok[k]) continue;
+    const int g = gq[k], nd = ndq[k], gn = node0 + nd;
+    const int j = gn / G.nx, i = gn - j * G.nx;
+    const bool bnd = node_type(j, i, G.nx, G.ny) != 0;
+    const T A = As[nd], B = Bs[nd];
+    Quad<T> p1, wq;
+    double pa = 0.0, pb = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int s = g * kGroup + r;
+      const T w = Wb[nd * LS + s], S = Sb[nd * LS + s];
+      T p = v1[k].v[r] + cdt * (B * S - (A + B) * w);
+      if (bnd) {
+        // detector misfit enters through the outgoing boundary entries
+        const int64_t ib4 = ((int64_t)q * G.K1 + a.step) * 4;
+        if (i == 0) p += T(a.kappa[0 * G.M + s] * a.inj[(ib4 + 0) * G.npos + j]);
+        if (i == G.nx - 1) p += T(a.kappa[1 * G.M + s] * a.inj[(ib4 + 1) * G.npos + j]);
+        if (j == 0) p += T(a.kappa[2 * G.M + s] * a.inj[(ib4 + 2) * G.npos + i]);
+        if (j == G.ny - 1) p += T(a.kappa[3 * G.M + s] * a.inj[(ib4 + 3) * G.npos + i]);
+      }
+      p1.v[r] = p;
+      wq.v[r] = w;
+      pa += (double)uq[k].v[r] * (double)w;
+      pb += (double)uq[k].v[r] * ((double)S - (double)w);
+    }
+    const int64_t off = ib + g * G.grp_stride + (int64_t)gn * kGroup;
+    stq(a.p_out + off, p1);
+    stq(a.w_out + off, wq);
+    Pa[nd * G.G + g] = pa;
+    Pb[nd * G.G + g] = pb;
+  }
+  __syncthreads();
+
+  // per-node gradient sums over the groups (fixed order: deterministic)
   for (int nd = tid; nd < TN; nd += kNodeThreads) {
     const int gn = node0 + nd;
     if (gn >= Nn) continue;
     double sa = 0.0, sb = 0.0;
-    for (int s = 0; s < G.M; ++s) {
-      sa += (double)Vb[nd * LS + s];
-      sb += (double)Sb[nd * LS + s];
+    for (int g = 0; g < G.G; ++g) {
+      sa += Pa[nd * G.G + g];
+      sb += Pb[nd * G.G + g];
     }
     a.ga[(int64_t)q * Nn + gn] -= a.cdt * sa;
     a.gb[(int64_t)q * Nn + gn] += a.cdt * sb;
@@ -362,8 +445,16 @@ static hipError_t node_fwd_t(const Plan& p, const NodeFwdLaunch& L, hipStream_t 
   const int Nn = (int)(p.nx * p.ny);
   dim3 grid((unsigned)((Nn + TN - 1) / TN), (unsigned)p.Nq);
   const size_t sh = sizeof(T) * (size_t)(2 * TN * (p.Mpad + 1) + 2 * TN);
-  if (TN == 64) hipLaunchKernelGGL((node_fwd_kernel<T, 64>), grid, dim3(kNodeThreads), sh, s, a);
-  else hipLaunchKernelGGL((node_fwd_kernel<T, 32>), grid, dim3(kNodeThreads), sh, s, a);
+  const int qpt = (int)((p.G * TN + kNodeThreads - 1) / kNodeThreads);
+#define FWD_LAUNCH(TNV, Q) hipLaunchKernelGGL((node_fwd_kernel<T, TNV, Q>), grid, dim3(kNodeThreads), sh, s, a)
+  if (TN == 64) {
+    switch (qpt) { case 1: FWD_LAUNCH(64, 1); break; case 2: FWD_LAUNCH(64, 2); break;
+                   case 3: FWD_LAUNCH(64, 3); break; default: FWD_LAUNCH(64, 4); break; }
+  } else {
+    switch (qpt) { case 1: FWD_LAUNCH(32, 1); break; case 2: FWD_LAUNCH(32, 2); break;
+                   case 3: FWD_LAUNCH(32, 3); break; default: FWD_LAUNCH(32, 4); break; }
+  }
+#undef FWD_LAUNCH
   return hipGetLastError();
 }
 
@@ -385,9 +476,17 @@ static hipError_t node_adj_t(const Plan& p, const NodeAdjLaunch& L, hipStream_t 
   const int TN = node_tile<T>(p);
   const int Nn = (int)(p.nx * p.ny);
   dim3 grid((unsigned)((Nn + TN - 1) / TN), (unsigned)p.Nq);
-  const size_t sh = sizeof(T) * (size_t)(3 * TN * (p.Mpad + 1) + 2 * TN);
-  if (TN == 64) hipLaunchKernelGGL((node_adj_kernel<T, 64>), grid, dim3(kNodeThreads), sh, s, a);
-  else hipLaunchKernelGGL((node_adj_kernel<T, 32>), grid, dim3(kNodeThreads), sh, s, a);
+  const size_t sh = sizeof(T) * (size_t)(3 * TN * (p.Mpad + 1) + 2 * TN + 2) + sizeof(double) * 2 * TN * p.G;
+  const int qpt = (int)((p.G * TN + kNodeThreads - 1) / kNodeThreads);
+#define ADJ_LAUNCH(TNV, Q) hipLaunchKernelGGL((node_adj_kernel<T, TNV, Q>), grid, dim3(kNodeThreads), sh, s, a)
+  if (TN == 64) {
+    switch (qpt) { case 1: ADJ_LAUNCH(64, 1); break; case 2: ADJ_LAUNCH(64, 2); break;
+                   case 3: ADJ_LAUNCH(64, 3); break; default: ADJ_LAUNCH(64, 4); break; }
+  } else {
+    switch (qpt) { case 1: ADJ_LAUNCH(32, 1); break; case 2: ADJ_LAUNCH(32, 2); break;
+                   case 3: ADJ_LAUNCH(32, 3); break; default: ADJ_LAUNCH(32, 4); break; }
+  }
+#undef ADJ_LAUNCH
   return hipGetLastError();
 }
 
