@@ -140,6 +140,31 @@ int rte_gradient(rte_plan* plan, const void* mu_a, const void* mu_s, const doubl
                  double* J, double* dmu_a, double* dmu_s, double* G, void* workspace,
                  int64_t workspace_bytes, void* stream);
 
+/* Graph mode.  With enable != 0, rte_gradient records its whole launch
+ * sequence (forward, misfit, adjoint: ~6 kernels per time step) into one HIP
+ * graph on first use and replays it while the argument pointers and the
+ * workspace size stay the same; any change re-records.  Profiling events are
+ * not recorded into the graph.  enable == 0 frees the graph.              */
+int rte_plan_set_graph(rte_plan* plan, int enable);
+
+/* A batch of independent plans of any sizes (uneven grids, ordinate counts,
+ * step counts; multiple-staggered-source combinations or separate
+ * instances).  The batch refers to the plans; they must outlive it.       */
+typedef struct rte_batch rte_batch;
+int rte_batch_create(rte_plan* const* plans, int64_t n, rte_batch** out);
+int rte_batch_destroy(rte_batch* batch);
+
+/* rte_gradient of every plan of the batch in ONE graph launch on `stream`:
+ * each instance is a branch of the graph, so small instances run alongside
+ * large ones.  Every argument is an array of n entries with the meaning of
+ * the rte_gradient argument of the same name; each instance needs its own
+ * workspace.  The graph is recorded on the first call and replayed while all
+ * pointers stay the same.                                                  */
+int rte_batch_gradient(rte_batch* batch, const void* const* mu_a, const void* const* mu_s,
+                       const double* const* G_meas, double* const* J, double* const* dmu_a,
+                       double* const* dmu_s, double* const* G, void* const* workspaces,
+                       const int64_t* workspace_bytes, void* stream);
+
 /* Instrumentation.  Kernel classes of one time step: */
 typedef enum {
   RTE_K_LINE_X_FWD = 0, /* x-line FC derivative                       */

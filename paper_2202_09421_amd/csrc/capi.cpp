@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <sstream>
+#include <string>
+#include <vector>
 
 #include "rte_internal.h"
 
@@ -103,20 +105,20 @@ int run_forward(Plan& p, const void* mu_a, const void* mu_s, double* G, void* u_
   const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
   Ctx c{p, ws, st, mu_a, mu_s, S};
   p.have_forward = false;
-  for (int k = 0; k < 3; ++k) RTE_CHECK(hipMemsetAsync(ws.lring[k], 0, S, st));
-  RTE_CHECK(hipMemsetAsync(ws.flux, 0, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
+  for (int k = 0; k < 3; ++k) RTE_CHECK(launch_zero(ws.lring[k], S, st));
+  RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
   const bool store_all = save && p.ckpt_every == 0;
   const int64_t s = p.ckpt_every;
   void* u0 = store_all ? ws.states : ws.work_u[0];
-  RTE_CHECK(hipMemsetAsync(u0, 0, S, st));
+  RTE_CHECK(launch_zero(u0, S, st));
   void* un = u0;
   for (int n = 0; n < p.K; ++n) {
     if (save && s > 0 && n % s == 0) {
       void* ck = at(ws.ckpts, (n / s) * 4, S);
-      RTE_CHECK(hipMemcpyAsync(ck, un, S, hipMemcpyDeviceToDevice, st));
-      RTE_CHECK(hipMemcpyAsync(at(ck, 1, S), ws.lring[(n + 2) % 3], S, hipMemcpyDeviceToDevice, st));
-      RTE_CHECK(hipMemcpyAsync(at(ck, 2, S), ws.lring[(n + 1) % 3], S, hipMemcpyDeviceToDevice, st));
-      RTE_CHECK(hipMemcpyAsync(at(ck, 3, S), ws.lring[n % 3], S, hipMemcpyDeviceToDevice, st));
+      RTE_CHECK(launch_copy(ck, un, S, st));
+      RTE_CHECK(launch_copy(at(ck, 1, S), ws.lring[(n + 2) % 3], S, st));
+      RTE_CHECK(launch_copy(at(ck, 2, S), ws.lring[(n + 1) % 3], S, st));
+      RTE_CHECK(launch_copy(at(ck, 3, S), ws.lring[n % 3], S, st));
     }
     void* unp1 = store_all ? at(ws.states, n + 1, S) : ws.work_u[(n + 1) & 1];
     int rc = fwd_step(c, n, un, unp1, ws.flux);
@@ -148,10 +150,10 @@ int run_adjoint(Plan& p, const void* mu_a, const void* mu_s, const double* Gbar,
   Ctx c{p, ws, st, mu_a, mu_s, S};
   const int K = (int)p.K;
   RTE_CHECK(launch_inject(p, Gbar, ws.flux, K, st));
-  for (int k = 0; k < 4; ++k) RTE_CHECK(hipMemsetAsync(ws.vring[k], 0, S, st));
+  for (int k = 0; k < 4; ++k) RTE_CHECK(launch_zero(ws.vring[k], S, st));
   const int64_t gbytes = p.Nq * p.nx * p.ny * 8;
-  RTE_CHECK(hipMemsetAsync(ws.ga, 0, gbytes, st));
-  RTE_CHECK(hipMemsetAsync(ws.gb, 0, gbytes, st));
+  RTE_CHECK(launch_zero(ws.ga, gbytes, st));
+  RTE_CHECK(launch_zero(ws.gb, gbytes, st));
   if (p.ckpt_every == 0) {
     for (int n = K; n >= 1; --n) {
       int rc = adj_step(c, n, at(ws.states, n, S));
@@ -163,10 +165,10 @@ int run_adjoint(Plan& p, const void* mu_a, const void* mu_s, const double* Gbar,
     for (int j = nseg - 1; j >= 0; --j) {
       const int k0 = j * s, k1 = std::min(k0 + s, K);
       void* ck = at(ws.ckpts, (int64_t)j * 4, S);
-      RTE_CHECK(hipMemcpyAsync(ws.states, ck, S, hipMemcpyDeviceToDevice, st));
-      RTE_CHECK(hipMemcpyAsync(ws.lring[(k0 + 2) % 3], at(ck, 1, S), S, hipMemcpyDeviceToDevice, st));
-      RTE_CHECK(hipMemcpyAsync(ws.lring[(k0 + 1) % 3], at(ck, 2, S), S, hipMemcpyDeviceToDevice, st));
-      RTE_CHECK(hipMemcpyAsync(ws.lring[k0 % 3], at(ck, 3, S), S, hipMemcpyDeviceToDevice, st));
+      RTE_CHECK(launch_copy(ws.states, ck, S, st));
+      RTE_CHECK(launch_copy(ws.lring[(k0 + 2) % 3], at(ck, 1, S), S, st));
+      RTE_CHECK(launch_copy(ws.lring[(k0 + 1) % 3], at(ck, 2, S), S, st));
+      RTE_CHECK(launch_copy(ws.lring[k0 % 3], at(ck, 3, S), S, st));
       for (int k = k0; k < k1; ++k) {
         int rc = fwd_step(c, k, at(ws.states, k - k0, S), at(ws.states, k + 1 - k0, S), nullptr);
         if (rc != RTE_OK) return rc;
@@ -180,6 +182,71 @@ int run_adjoint(Plan& p, const void* mu_a, const void* mu_s, const double* Gbar,
   RTE_CHECK(launch_grad_reduce(p, ws.ga, ws.gb, da, db, st));
   return RTE_OK;
 }
+
+struct GradArgs {
+  const void* mu_a;
+  const void* mu_s;
+  const double* G_meas;
+  double* J;
+  double* dmu_a;
+  double* dmu_s;
+  double* G;
+  void* ws;
+  int64_t wsb;
+};
+
+// Forward with kept states, misfit and cotangent, adjoint: all enqueued on st.
+int enqueue_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
+  int rc = run_forward(p, a.mu_a, a.mu_s, a.G, nullptr, 1, a.ws, a.wsb, st);
+  if (rc != RTE_OK) return rc;
+  Workspace ws;
+  map_workspace(p, a.ws, a.wsb, true, &ws);
+  RTE_CHECK(launch_misfit(p, a.G, a.G_meas, ws.gbar, a.J, (int)p.K, st));
+  return run_adjoint(p, a.mu_a, a.mu_s, ws.gbar, a.dmu_a, a.dmu_s, a.ws, a.wsb, st);
+}
+
+// Graph mode: record the whole sequence once per argument set, then replay.
+int graph_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
+  const void* key[9] = {a.mu_a, a.mu_s, a.G_meas, a.J, a.dmu_a, a.dmu_s, a.G, a.ws, nullptr};
+  bool same = p.gexec != nullptr && p.gkey_bytes == a.wsb;
+  for (int k = 0; k < 8 && same; ++k) same = (p.gkey[k] == key[k]);
+  if (!same) {
+    if (p.gexec) {
+      RTE_CHECK(hipGraphExecDestroy(p.gexec));
+      p.gexec = nullptr;
+    }
+    if (!p.cap_stream) RTE_CHECK(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
+    const bool prof = p.prof;
+    p.prof = false;  // no event nodes in the recorded graph
+    RTE_CHECK(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_gradient(p, a, p.cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p.cap_stream, &graph);
+    p.prof = prof;
+    if (rc != RTE_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    RTE_CHECK(ec);
+    const hipError_t ei = hipGraphInstantiate(&p.gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    RTE_CHECK(ei);
+    for (int k = 0; k < 8; ++k) p.gkey[k] = key[k];
+    p.gkey_bytes = a.wsb;
+  }
+  RTE_CHECK(hipGraphLaunch(p.gexec, st));
+  p.have_forward = true;
+  return RTE_OK;
+}
+
+struct Batch {
+  std::vector<Plan*> plans;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  hipStream_t s0 = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const void*> key;
+};
 
 bool nonnull(const void* p, const char* what) {
   if (!p) {
@@ -260,13 +327,129 @@ int rte_gradient(rte_plan* h, const void* mu_a, const void* mu_s, const double* 
   try {
     set_error("");
     Plan& p = *reinterpret_cast<Plan*>(h);
+    GradArgs a{mu_a, mu_s, G_meas, J, dmu_a, dmu_s, G, workspace, workspace_bytes};
     hipStream_t st = static_cast<hipStream_t>(stream);
-    int rc = run_forward(p, mu_a, mu_s, G, nullptr, 1, workspace, workspace_bytes, st);
-    if (rc != RTE_OK) return rc;
-    Workspace ws;
-    map_workspace(p, workspace, workspace_bytes, true, &ws);
-    RTE_CHECK(launch_misfit(p, G, G_meas, ws.gbar, J, (int)p.K, st));
-    return run_adjoint(p, mu_a, mu_s, ws.gbar, dmu_a, dmu_s, workspace, workspace_bytes, st);
+    if (p.use_graph) return graph_gradient(p, a, st);
+    return enqueue_gradient(p, a, st);
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RTE_EINVAL;
+  }
+}
+
+int rte_plan_set_graph(rte_plan* h, int enable) {
+  if (!nonnull(h, "plan")) return RTE_EINVAL;
+  Plan& p = *reinterpret_cast<Plan*>(h);
+  p.use_graph = enable != 0;
+  if (!p.use_graph && p.gexec) {
+    RTE_CHECK(hipGraphExecDestroy(p.gexec));
+    p.gexec = nullptr;
+  }
+  return RTE_OK;
+}
+
+int rte_batch_create(rte_plan* const* plans, int64_t n, rte_batch** out) {
+  if (!nonnull(plans, "plans") || !nonnull(out, "out")) return RTE_EINVAL;
+  *out = nullptr;
+  if (n < 1 || n > 1024) {
+    set_error("batch size must be in [1, 1024]");
+    return RTE_EINVAL;
+  }
+  Batch* b = new Batch();
+  for (int64_t i = 0; i < n; ++i) {
+    if (!plans[i]) {
+      delete b;
+      set_error("plan entry is NULL");
+      return RTE_EINVAL;
+    }
+    b->plans.push_back(reinterpret_cast<Plan*>(plans[i]));
+  }
+  *out = reinterpret_cast<rte_batch*>(b);
+  return RTE_OK;
+}
+
+int rte_batch_destroy(rte_batch* h) {
+  if (!h) return RTE_OK;
+  Batch* b = reinterpret_cast<Batch*>(h);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  if (b->s0) (void)hipStreamDestroy(b->s0);
+  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+  delete b;
+  return RTE_OK;
+}
+
+int rte_batch_gradient(rte_batch* h, const void* const* mu_a, const void* const* mu_s, const double* const* G_meas,
+                       double* const* J, double* const* dmu_a, double* const* dmu_s, double* const* G,
+                       void* const* workspaces, const int64_t* ws_bytes, void* stream) {
+  if (!nonnull(h, "batch") || !nonnull(mu_a, "mu_a") || !nonnull(mu_s, "mu_s") || !nonnull(G_meas, "G_meas") ||
+      !nonnull(J, "J") || !nonnull(dmu_a, "dmu_a") || !nonnull(dmu_s, "dmu_s") || !nonnull(G, "G") ||
+      !nonnull(workspaces, "workspaces") || !nonnull(ws_bytes, "ws_bytes"))
+    return RTE_EINVAL;
+  try {
+    set_error("");
+    Batch& b = *reinterpret_cast<Batch*>(h);
+    const size_t n = b.plans.size();
+    std::vector<GradArgs> args(n);
+    std::vector<const void*> key;
+    for (size_t i = 0; i < n; ++i) {
+      args[i] = GradArgs{mu_a[i], mu_s[i], G_meas[i], J[i], dmu_a[i], dmu_s[i], G[i], workspaces[i], ws_bytes[i]};
+      if (!args[i].mu_a || !args[i].mu_s || !args[i].G_meas || !args[i].J || !args[i].dmu_a || !args[i].dmu_s ||
+          !args[i].G || !args[i].ws) {
+        set_error("a pointer of batch entry " + std::to_string(i) + " is NULL");
+        return RTE_EINVAL;
+      }
+      const void* k[9] = {args[i].mu_a, args[i].mu_s, args[i].G_meas, args[i].J, args[i].dmu_a, args[i].dmu_s,
+                          args[i].G, args[i].ws, reinterpret_cast<const void*>(args[i].wsb)};
+      key.insert(key.end(), k, k + 9);
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!b.gexec || key != b.key) {
+      if (b.gexec) {
+        RTE_CHECK(hipGraphExecDestroy(b.gexec));
+        b.gexec = nullptr;
+      }
+      if (!b.s0) RTE_CHECK(hipStreamCreateWithFlags(&b.s0, hipStreamNonBlocking));
+      while (b.streams.size() < n) {
+        hipStream_t s;
+        RTE_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        b.streams.push_back(s);
+      }
+      while (b.events.size() < n + 1) {
+        hipEvent_t e;
+        RTE_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b.events.push_back(e);
+      }
+      // one captured graph: fork one branch per instance, join at the end
+      RTE_CHECK(hipStreamBeginCapture(b.s0, hipStreamCaptureModeThreadLocal));
+      int rc = RTE_OK;
+      hipError_t e = hipEventRecord(b.events[n], b.s0);
+      for (size_t i = 0; i < n && rc == RTE_OK && e == hipSuccess; ++i) {
+        e = hipStreamWaitEvent(b.streams[i], b.events[n], 0);
+        if (e != hipSuccess) break;
+        const bool prof = b.plans[i]->prof;
+        b.plans[i]->prof = false;
+        rc = enqueue_gradient(*b.plans[i], args[i], b.streams[i]);
+        b.plans[i]->prof = prof;
+        if (rc != RTE_OK) break;
+        e = hipEventRecord(b.events[i], b.streams[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b.s0, b.events[i], 0);
+      }
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(b.s0, &graph);
+      if (rc != RTE_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      RTE_CHECK(e);
+      RTE_CHECK(ec);
+      const hipError_t ei = hipGraphInstantiate(&b.gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      RTE_CHECK(ei);
+      b.key = key;
+    }
+    RTE_CHECK(hipGraphLaunch(b.gexec, st));
+    return RTE_OK;
   } catch (const std::exception& e) {
     set_error(e.what());
     return RTE_EINVAL;

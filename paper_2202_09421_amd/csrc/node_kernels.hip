@@ -16,6 +16,8 @@
 //   P1   = v^{n+1} + c dt (b W w - (a + b) w) + D_e^T Gbar^n
 //   dJ/da += -c dt sum_m u^n_m w_m,   dJ/db += c dt sum_m u^n_m ((W w)_m - w_m)
 // The line passes then add -c dt (Dx^T(xi w) + Dy^T(eta w)) to P1.
+#include <algorithm>
+
 #include "rte_internal.h"
 
 namespace rte {
@@ -570,6 +572,32 @@ __global__ void unpermute_kernel(const T* __restrict__ st, T* __restrict__ out, 
   const int g = s / kGroup, r = s % kGroup;
   const T v = st[(int64_t)q * G * Nn * kGroup + (int64_t)g * Nn * kGroup + gn * kGroup + r];
   out[((int64_t)q * Nn + gn) * M + slot_m[s]] = v;
+}
+
+// Zero fill and device copy as kernels (8-byte words): graph captures of the
+// step sequence then hold only kernel nodes.
+__global__ void fill_zero_kernel(unsigned long long* __restrict__ p, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) p[t] = 0ull;
+}
+__global__ void copy_words_kernel(unsigned long long* __restrict__ d, const unsigned long long* __restrict__ s, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) d[t] = s[t];
+}
+
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s) {
+  const int64_t n = bytes / 8;
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(256), 0, s, (unsigned long long*)p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void* d, const void* src, int64_t bytes, hipStream_t s) {
+  const int64_t n = bytes / 8;
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(copy_words_kernel, dim3(blocks), dim3(256), 0, s, (unsigned long long*)d,
+                     (const unsigned long long*)src, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_detect(const Plan& p, const double* flux, double* G, int K, hipStream_t s) {

@@ -440,6 +440,8 @@ int plan_destroy(rte_plan* h) {
       (void)hipEventDestroy(e.second);
     }
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   delete p;
   return RTE_OK;
 }

@@ -90,6 +90,12 @@ struct Plan {
   int64_t ckpt_every = 0;
   bool have_forward = false;   // a saved forward lives in the workspace
   int64_t saved_K = 0;
+  // graph mode: rte_gradient recorded once per argument set, then replayed
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* gkey[9] = {nullptr};
+  int64_t gkey_bytes = 0;
   // instrumentation: event pairs per kernel class
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -185,5 +191,7 @@ hipError_t launch_misfit(const Plan& p, const double* G, const double* Gm, doubl
 hipError_t launch_grad_reduce(const Plan& p, const double* ga, const double* gb, double* da, double* db,
                               hipStream_t s);
 hipError_t launch_unpermute(const Plan& p, const void* state, void* out, hipStream_t s);
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
+hipError_t launch_copy(void* d, const void* src, int64_t bytes, hipStream_t s);
 
 }  // namespace rte

@@ -75,11 +75,17 @@ def lib():
         L.rte_forward.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp, i64, vp]
         L.rte_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp]
         L.rte_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.rte_plan_set_graph.argtypes = [vp, ctypes.c_int]
+        L.rte_batch_create.argtypes = [ctypes.POINTER(vp), i64, ctypes.POINTER(vp)]
+        L.rte_batch_destroy.argtypes = [vp]
+        pp = ctypes.POINTER(vp)
+        L.rte_batch_gradient.argtypes = [vp, pp, pp, pp, pp, pp, pp, pp, pp, ctypes.POINTER(i64), vp]
         L.rte_profile_enable.argtypes = [vp, ctypes.c_int]
         L.rte_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.rte_last_error.restype = ctypes.c_char_p
         for f in ("rte_plan_create", "rte_plan_destroy", "rte_plan_info", "rte_workspace_bytes", "rte_forward",
-                  "rte_adjoint", "rte_gradient", "rte_profile_enable", "rte_profile_read"):
+                  "rte_adjoint", "rte_gradient", "rte_profile_enable", "rte_profile_read", "rte_plan_set_graph",
+                  "rte_batch_create", "rte_batch_destroy", "rte_batch_gradient"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -140,6 +146,8 @@ class Plan:
         _check(lib().rte_plan_info(h, ctypes.byref(Nq), ctypes.byref(Nd), ctypes.byref(Npx), ctypes.byref(Npy)))
         self.Nq, self.Nd, self.Np_x, self.Np_y = Nq.value, Nd.value, Npx.value, Npy.value
         self._ws = None
+        self._graph = False
+        self._gout = None
 
     def close(self):
         if getattr(self, "_h", None):
@@ -199,17 +207,79 @@ class Plan:
                                  _stream()))
         return da, db
 
+    def set_graph(self, on=True):
+        """Graph mode: rte_gradient is recorded once per argument set and
+        replayed.  Outputs then live in buffers owned by the plan (reused by
+        every call: copy them to keep a result across calls), and inputs must
+        be the same tensors from call to call to avoid re-recording."""
+        _check(lib().rte_plan_set_graph(self._h, 1 if on else 0))
+        self._graph = bool(on)
+
+    def _outputs(self):
+        ny, nx = self.spec.Ny + 1, self.spec.Nx + 1
+        mk = lambda *sh: torch.empty(sh, dtype=torch.float64, device=self.device)
+        if not self._graph:
+            return mk(1), mk(ny, nx), mk(ny, nx), mk(self.Nq, self.Nd, self.spec.K)
+        if self._gout is None:
+            self._gout = (mk(1), mk(ny, nx), mk(ny, nx), mk(self.Nq, self.Nd, self.spec.K))
+        return self._gout
+
     def gradient(self, mu_a, mu_s, G_meas):
         a, b = self._medium(mu_a, mu_s)
         gm = torch.as_tensor(G_meas, dtype=torch.float64, device=self.device).contiguous()
-        ny, nx = self.spec.Ny + 1, self.spec.Nx + 1
-        J = torch.empty((1,), dtype=torch.float64, device=self.device)
-        da = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
-        db = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
-        G = torch.empty((self.Nq, self.Nd, self.spec.K), dtype=torch.float64, device=self.device)
+        J, da, db, G = self._outputs()
         ws = self.workspace(True)
         _check(lib().rte_gradient(self._h, _ptr(a), _ptr(b), _ptr(gm), _ptr(J), _ptr(da), _ptr(db), _ptr(G),
                                   _ptr(ws), ws.numel(), _stream()))
+        return J, da, db, G
+
+
+class Batch:
+    """Uneven batch: rte_gradient of several plans in one graph launch.
+    Inputs must stay the same tensors between calls (the graph is replayed
+    while every pointer is unchanged); outputs are owned by the batch."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        hs = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().rte_batch_create(hs, len(self.plans), ctypes.byref(h)))
+        self._h = h
+        self._out = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rte_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def gradient(self, media, G_meas):
+        """media: list of (mu_a, mu_s); G_meas: list.  Returns lists J, dmu_a, dmu_s, G."""
+        n = len(self.plans)
+        ins = [p._medium(a, b) for p, (a, b) in zip(self.plans, media)]
+        gms = [torch.as_tensor(g, dtype=torch.float64, device=p.device).contiguous() for p, g in zip(self.plans, G_meas)]
+        if self._out is None:
+            self._out = [p._outputs() if p._graph else
+                         (lambda P: (torch.empty(1, dtype=torch.float64, device=P.device),
+                                     torch.empty((P.spec.Ny + 1, P.spec.Nx + 1), dtype=torch.float64, device=P.device),
+                                     torch.empty((P.spec.Ny + 1, P.spec.Nx + 1), dtype=torch.float64, device=P.device),
+                                     torch.empty((P.Nq, P.Nd, P.spec.K), dtype=torch.float64, device=P.device)))(p)
+                         for p in self.plans]
+        wss = [p.workspace(True) for p in self.plans]
+        self._keep = (ins, gms)
+        arr = lambda xs: (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        J = [o[0] for o in self._out]
+        da = [o[1] for o in self._out]
+        db = [o[2] for o in self._out]
+        G = [o[3] for o in self._out]
+        wb = (ctypes.c_int64 * n)(*[w.numel() for w in wss])
+        _check(lib().rte_batch_gradient(self._h, arr([x[0] for x in ins]), arr([x[1] for x in ins]), arr(gms),
+                                        arr(J), arr(da), arr(db), arr(G), arr(wss), wb, _stream()))
         return J, da, db, G
 
 

@@ -1,0 +1,100 @@
+"""GPU: graph-recorded gradients and uneven batches in one graph launch.
+
+A graph replays exactly the kernels of the eager path in the same order, so
+its results must equal the eager ones bit for bit.  Each replay is checked,
+with eager work on other plans and a synchronisation between replays."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rte():
+    from paper_2202_09421_amd import rte as R
+    R.lib()
+    return R
+
+
+def _gm(spec, seed):
+    rng = np.random.default_rng(seed)
+    return torch.tensor(1e-3 * rng.standard_normal((spec.Nq, len(spec.detectors), spec.K)), device="cuda")
+
+
+def _eager(rte, spec, ckpt=0):
+    plan = rte.Plan(spec, torch.float64, ckpt_every=ckpt)
+    J, ga, gb, G = plan.gradient(spec.mu_a, spec.mu_s, _gm(spec, 1))
+    torch.cuda.synchronize()
+    return [x.cpu().numpy().copy() for x in (J, ga, gb, G)]
+
+
+def test_graph_replays_equal_eager(rte):
+    spec = W.small_problem(N=24, M=16, K=40, seed=3, n_in=1.4)
+    ref = _eager(rte, spec)
+    other = W.small_problem(N=16, M=8, K=20, seed=4)
+    plan = rte.Plan(spec, torch.float64)
+    plan.set_graph(True)
+    a = torch.tensor(spec.mu_a, device="cuda")
+    b = torch.tensor(spec.mu_s, device="cuda")
+    gm = _gm(spec, 1)
+    for rep in range(4):
+        say("graph replay", rep)
+        J, ga, gb, G = plan.gradient(a, b, gm)
+        torch.cuda.synchronize()
+        got = [x.cpu().numpy() for x in (J, ga, gb, G)]
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), rep
+        _eager(rte, other)          # unrelated eager work between replays
+        torch.zeros(1 << 20, device="cuda").add_(1.0)
+        torch.cuda.synchronize()
+
+
+def test_uneven_batch_one_launch_equals_individual(rte):
+    specs = [
+        W.small_problem(N=24, M=16, K=40, seed=3, n_in=1.4),
+        W.small_problem(N=12, M=8, K=25, seed=5),
+        W.small_problem(N=20, M=12, K=60, seed=6, Ny=14, g=0.7),
+        W.small_problem(N=64, M=32, K=15, seed=7, n_in=1.4, g=0.9),
+    ]
+    ckpts = [0, 0, 7, 0]
+    refs = [_eager(rte, s, c) for s, c in zip(specs, ckpts)]
+    plans = [rte.Plan(s, torch.float64, ckpt_every=c) for s, c in zip(specs, ckpts)]
+    batch = rte.Batch(plans)
+    media = [(torch.tensor(s.mu_a, device="cuda"), torch.tensor(s.mu_s, device="cuda")) for s in specs]
+    gms = [_gm(s, 1) for s in specs]
+    for rep in range(3):
+        say("batch launch", rep)
+        J, ga, gb, G = batch.gradient(media, gms)
+        torch.cuda.synchronize()
+        for i, ref in enumerate(refs):
+            got = [J[i].cpu().numpy(), ga[i].cpu().numpy(), gb[i].cpu().numpy(), G[i].cpu().numpy()]
+            for x, y in zip(got, ref):
+                assert np.array_equal(x, y), (rep, i)
+        _eager(rte, specs[1])
+        torch.cuda.synchronize()
+
+
+def test_graph_gradient_workload_equals_eager(rte):
+    # the benchmark's configuration, graph mode vs eager
+    spec = W.config(1)
+    say("graph on", spec.name)
+    plan = rte.Plan(spec, torch.float64)
+    a = torch.full((spec.Ny + 1, spec.Nx + 1), 0.2, dtype=torch.float64, device="cuda")
+    b = torch.full((spec.Ny + 1, spec.Nx + 1), 50.0, dtype=torch.float64, device="cuda")
+    gm = _gm(spec, 2)
+    J0, ga0, gb0, G0 = [x.clone() for x in plan.gradient(a, b, gm)]
+    plan.set_graph(True)
+    for rep in range(2):
+        J, ga, gb, G = plan.gradient(a, b, gm)
+        torch.cuda.synchronize()
+        assert torch.equal(J, J0) and torch.equal(ga, ga0) and torch.equal(gb, gb0) and torch.equal(G, G0), rep
