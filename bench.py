@@ -31,20 +31,17 @@ WORD = {"f64": 8, "f32": 4}
 
 # compulsory words moved per unit (node x ordinate) by one launch of each kernel class
 KERNEL_WORDS = {
-    "line_x_fwd": 2,   # read u, write -xi Dx u
-    "line_y_fwd": 3,   # read u and the x term, write the advection term
-    "node_fwd": 7,     # read u, T, L^{n-1..n-3}; write u^{n+1}, L^n
-    "node_adj": 7,     # read v^{n+1..n+4}, u^n; write w, P1
-    "line_x_adj": 2,   # read w, write Dx^T(xi w)
-    "line_y_adj": 4,   # read w, the x term, P1; write ubar^n
+    "lines_fwd": 4,    # x and y lines: read u twice, write -xi Dx u and -eta Dy u
+    "node_fwd": 8,     # read u, X, Y, L^{n-1..n-3}; write u^{n+1}, L^n
+    "node_adj": 10,    # read atx, aty, P1^{n+1}, v^{n+2..n+4}, u^n; write v^{n+1}, w^n, P1^n
+    "lines_adj": 4,    # x and y lines: read w twice, write Dx^T(xi w) and Dy^T(eta w)
 }
 PATH_WORDS_STORE_ALL = 12  # algorithmic fwd + adj per unit: 6 + 6 words
 
 # kernel class -> row label in the committed HBM counter summary
 TRAFFIC_ROWS = {
-    "line_x_fwd": "x-line derivative (fwd)", "line_y_fwd": "y-line derivative (fwd)",
-    "node_fwd": "node pass (fwd)", "node_adj": "node pass (adj)",
-    "line_x_adj": "x-line transpose (adj)", "line_y_adj": "y-line transpose (adj)",
+    "lines_fwd": "x and y line derivatives (fwd)", "node_fwd": "node pass (fwd)",
+    "node_adj": "node pass (adj)", "lines_adj": "x and y line transposes (adj)",
 }
 TRAFFIC_FILE = {"f64": "profiles/gradient_fp64_257x257_M32_K2000_hbm_traffic.md"}
 

@@ -167,13 +167,11 @@ int rte_batch_gradient(rte_batch* batch, const void* const* mu_a, const void* co
 
 /* Instrumentation.  Kernel classes of one time step: */
 typedef enum {
-  RTE_K_LINE_X_FWD = 0, /* x-line FC derivative                       */
-  RTE_K_LINE_Y_FWD = 1, /* y-line FC derivative                       */
-  RTE_K_NODE_FWD = 2,   /* scattering, AB4, inflow condition, flux    */
-  RTE_K_NODE_ADJ = 3,   /* adjoint node pass and gradient accumulation */
-  RTE_K_LINE_X_ADJ = 4, /* x-line transposed derivative               */
-  RTE_K_LINE_Y_ADJ = 5, /* y-line transposed derivative + combination */
-  RTE_K_COUNT = 6
+  RTE_K_LINES_FWD = 0, /* FC derivatives along x and y lines          */
+  RTE_K_NODE_FWD = 1,  /* scattering, AB4, inflow condition, flux     */
+  RTE_K_NODE_ADJ = 2,  /* adjoint node pass and gradient accumulation  */
+  RTE_K_LINES_ADJ = 3, /* transposed FC derivatives along x and y     */
+  RTE_K_COUNT = 4
 } rte_kernel_class;
 
 /* enable != 0: every later launch of a time-step kernel on this plan is

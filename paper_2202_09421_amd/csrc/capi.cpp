@@ -44,15 +44,14 @@ inline void* at(void* base, int64_t k, int64_t S) { return static_cast<char*>(ba
     RTE_CHECK(prof_end(stop_, c.st));             \
   } while (0)
 
-// One forward step u^n -> u^{n+1}: x lines, y lines, node update.
+// One forward step u^n -> u^{n+1}: x and y lines (one launch), node update.
 int fwd_step(Ctx& c, int n, const void* un, void* unp1, double* flux) {
-  LineLaunch lx{un, nullptr, nullptr, c.ws.tx, LINE_FWD_X, 0, 0.0};
-  TIMED(RTE_K_LINE_X_FWD, launch_line(c.p, lx, c.st));
-  LineLaunch ly{un, c.ws.tx, nullptr, c.ws.tt, LINE_FWD_Y, 1, 0.0};
-  TIMED(RTE_K_LINE_Y_FWD, launch_line(c.p, ly, c.st));
+  LineLaunch ll{un, c.ws.tx, c.ws.ty, LINE_FWD, 3};
+  TIMED(RTE_K_LINES_FWD, launch_lines(c.p, ll, c.st));
   NodeFwdLaunch nf;
   nf.u = un;
-  nf.T = c.ws.tt;
+  nf.X = c.ws.tx;
+  nf.Y = c.ws.ty;
   nf.L1 = c.ws.lring[(n + 2) % 3];
   nf.L2 = c.ws.lring[(n + 1) % 3];
   nf.L3 = c.ws.lring[n % 3];
@@ -66,11 +65,15 @@ int fwd_step(Ctx& c, int n, const void* un, void* unp1, double* flux) {
   return RTE_OK;
 }
 
-// One adjoint step n (K..1) given u^n.
+// One adjoint step n (K..1) given u^n: node pass (forms v^{n+1} from the
+// carried pieces of ubar^{n+1}, then w^n, P1^n and the gradient terms), then
+// the transposed line derivatives of w^n, carried to step n-1.
 int adj_step(Ctx& c, int n, const void* un) {
-  const double cdt = c.p.prob.c * c.p.prob.dt;
   NodeAdjLaunch na;
-  na.v1 = c.ws.vring[(n + 1) % 4];
+  na.atx = c.ws.atx;
+  na.aty = c.ws.aty;
+  na.ap1 = c.ws.ap1;
+  na.v1_out = c.ws.vring[(n + 1) % 4];
   na.v2 = c.ws.vring[(n + 2) % 4];
   na.v3 = c.ws.vring[(n + 3) % 4];
   na.v4 = c.ws.vring[n % 4];
@@ -79,16 +82,12 @@ int adj_step(Ctx& c, int n, const void* un) {
   na.mu_s = c.mu_s;
   na.inj = c.ws.flux;
   na.w_out = c.ws.wbuf;
-  na.p_out = c.ws.tt;
   na.ga = c.ws.ga;
   na.gb = c.ws.gb;
   na.step = n;
-  na.convert_v1 = (n + 1 <= c.p.K) ? 1 : 0;
   TIMED(RTE_K_NODE_ADJ, launch_node_adj(c.p, na, c.st));
-  LineLaunch lx{c.ws.wbuf, nullptr, nullptr, c.ws.tx, LINE_ADJ_X, 0, cdt};
-  TIMED(RTE_K_LINE_X_ADJ, launch_line(c.p, lx, c.st));
-  LineLaunch ly{c.ws.wbuf, c.ws.tx, c.ws.tt, c.ws.vring[n % 4], LINE_ADJ_Y, 1, cdt};
-  TIMED(RTE_K_LINE_Y_ADJ, launch_line(c.p, ly, c.st));
+  LineLaunch ll{c.ws.wbuf, c.ws.atx, c.ws.aty, LINE_ADJ, 3};
+  TIMED(RTE_K_LINES_ADJ, launch_lines(c.p, ll, c.st));
   return RTE_OK;
 }
 
@@ -150,7 +149,11 @@ int run_adjoint(Plan& p, const void* mu_a, const void* mu_s, const double* Gbar,
   Ctx c{p, ws, st, mu_a, mu_s, S};
   const int K = (int)p.K;
   RTE_CHECK(launch_inject(p, Gbar, ws.flux, K, st));
+  // zero adjoint ring and carries: ubar^{K+1} = 0, v^{K+2..K+4} = 0
   for (int k = 0; k < 4; ++k) RTE_CHECK(launch_zero(ws.vring[k], S, st));
+  RTE_CHECK(launch_zero(ws.atx, S, st));
+  RTE_CHECK(launch_zero(ws.aty, S, st));
+  RTE_CHECK(launch_zero(ws.ap1, S, st));
   const int64_t gbytes = p.Nq * p.nx * p.ny * 8;
   RTE_CHECK(launch_zero(ws.ga, gbytes, st));
   RTE_CHECK(launch_zero(ws.gb, gbytes, st));

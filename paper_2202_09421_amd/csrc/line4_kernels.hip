@@ -1,102 +1,169 @@
 // Four-step line passes for the common extended lengths N_p = N1 * N2.
 //
-// Same operation as line_kernels.hip (FC-Gram continuation + filtered
-// spectral derivative along x or y lines, or its transpose; Sec. 4.3), but
-// the DFT of length N_p is split as in the four-step algorithm:
+// FC-Gram continuation + filtered spectral derivative along x lines (rows)
+// and y lines (columns) of one state, or the exact transpose (Sec. 4.3).
+// The DFT of length N_p is split as in the four-step algorithm:
 //   A : N2 transforms of length N1 over the stride-N2 index, twiddle w^{n2 k1}
 //   B : N1 transforms of length N2 over each contiguous block, multiply by
 //       the derivative factor i mu_k at k = k1 + N1 k2, inverse length-N2
 //       transform, twiddle w^{-n2 k1}
 //   A': N2 inverse transforms of length N1
 // Each transform is a compile-time codelet held in registers, so a line makes
-// three LDS round trips instead of one per radix pass.  A workgroup is one
-// wave and handles four complex lines: two neighbouring lines (rows or
-// columns) of one ordinate group, each giving two complex lines.  LDS rows of
-// N2 entries are padded by one entry to spread the block reads of step B
-// over the banks.
+// three LDS round trips.
+//
+// Work unit: two neighbouring lines of one ordinate group (four complex
+// lines: slots r0 + i r1 and r2 + i r3 of each line, differentiated together
+// since the operator is real-linear).  A workgroup is one wave and handles
+// two consecutive units; every global load of both units, and of the FC
+// tables, is issued before the first one is transformed, so the memory
+// latency is paid once per wave.  x units come first, then y units; unit
+// pairs are even-aligned so a wave's two y units cover four adjacent
+// columns, i.e. whole 128-byte segments of the row-aligned state.
 #include "fft_codelets.h"
 #include "rte_internal.h"
 
 namespace rte {
 
 template <typename T>
-struct Line4Args {
+struct Lines4Args {
   const T* in;
-  const T* aux;
-  const T* aux2;
-  T* out;
-  const double* coef;
-  double cdt;
-  FcPlanDev fc;
-  int nlines;
-  int64_t line_stride, pt_stride, grp_stride, inst_stride;
+  T* out[2];
+  const double* coef[2];   // xi, eta in slot order
+  FcPlanDev fc;            // identical for every direction of the launch
+  int nlines[2];
+  int npe[2];              // line pairs per (source, group), rounded up to even
+  int64_t line_stride[2], pt_stride[2];
+  int64_t grp_stride, inst_stride;
+  int G;
+  int dir_first;           // direction of units [0, units_first)
+  int units_first;
+  int nunits;
 };
 
-// Block b runs on XCD b % 8; pairs 2x, 2x+1 of every chunk of 16 pairs go to
-// XCD x, so four neighbouring columns share one L2.
-__device__ __forceinline__ int remap_pair(int b) {
-  const int chunk = b >> 4, x = b & 7, k = (b >> 3) & 1;
-  return chunk * 16 + 2 * x + k;
+constexpr int kLP = 4;  // complex lines per unit
+constexpr size_t kLines4MaxLds = 64 * 1024;
+
+// lane-owned loads of one unit: point i of line it (0/1) for e = lane + 64 t,
+// i = e / 2, it = e % 2; 4 slots each
+template <typename T, int TMAX>
+struct UnitRegs {
+  T v[TMAX][4];
+};
+
+struct UnitDesc {
+  int dir;
+  bool live, has1;
+  int64_t base;
+  int s0;
+};
+
+template <typename T>
+__device__ __forceinline__ UnitDesc decode_unit(const Lines4Args<T>& a, int u) {
+  UnitDesc d;
+  int r = u;
+  d.dir = a.dir_first;
+  if (u >= a.units_first) {
+    d.dir = 1 - a.dir_first;
+    r = u - a.units_first;
+  }
+  const int npe = a.npe[d.dir];
+  const int pair = r % npe;
+  const int g = (r / npe) % a.G;
+  const int q = r / (npe * a.G);
+  const int line0 = 2 * pair;
+  d.live = (u < a.nunits) && (line0 < a.nlines[d.dir]);
+  d.has1 = line0 + 1 < a.nlines[d.dir];
+  d.base = (int64_t)q * a.inst_stride + (int64_t)g * a.grp_stride + (int64_t)line0 * a.line_stride[d.dir];
+  d.s0 = g * kGroup;
+  return d;
 }
 
-constexpr int kLP = 4;  // complex lines per workgroup
+template <typename T, int TMAX>
+__device__ __forceinline__ void load_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int lane,
+                                          UnitRegs<T, TMAX>& R) {
+  const T* in = a.in + d.base;
+  const int64_t ls = a.line_stride[d.dir], ps = a.pt_stride[d.dir];
+#pragma unroll
+  for (int t = 0; t < TMAX; ++t) {
+    const int e = lane + 64 * t, it = e & 1, i = e >> 1;
+    if (d.live && i < n && (it == 0 || d.has1)) {
+      const T* p = in + it * ls + (int64_t)i * ps;
+      if constexpr (sizeof(T) == 8) {
+        const double2 x = reinterpret_cast<const double2*>(p)[0];
+        const double2 y = reinterpret_cast<const double2*>(p)[1];
+        R.v[t][0] = x.x; R.v[t][1] = x.y; R.v[t][2] = y.x; R.v[t][3] = y.y;
+      } else {
+        const float4 x = *reinterpret_cast<const float4*>(p);
+        R.v[t][0] = x.x; R.v[t][1] = x.y; R.v[t][2] = x.z; R.v[t][3] = x.w;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) R.v[t][r] = T(0);
+    }
+  }
+}
 
-template <typename T, int MODE, int N1, int N2>
-__global__ __launch_bounds__(64) void line4_kernel(Line4Args<T> a) {
-  constexpr int N = N1 * N2;
-  constexpr int PS = N2 + 1;
-  constexpr int LSZ = N1 * PS;
-  constexpr bool adj = (MODE == LINE_ADJ_X || MODE == LINE_ADJ_Y);
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<double>* buf = reinterpret_cast<cx<double>*>(smem_raw);
-  cx<double>* cs = buf + kLP * LSZ;  // [l][end][kMaxFcD] and a second copy for the fold
+// LDS layout (doubles): buf [kLP][N1][N2+1] complex | cs [2][kLP][2][kMaxFcD]
+// complex | roots [N] complex | mu [N] | Q, A [kFcTab]
+template <int N1, int N2>
+struct L4Smem {
+  static constexpr int N = N1 * N2;
+  static constexpr int PS = N2 + 1;
+  static constexpr int LSZ = N1 * PS;
+  static constexpr int BUF = 2 * kLP * LSZ;
+  static constexpr int CS = 2 * 2 * kLP * 2 * kMaxFcD;
+  static constexpr int ROOTS = 2 * N;
+  static constexpr int MU = N;
+  static constexpr int TOTAL = BUF + CS + ROOTS + MU + kFcTab;
+  static constexpr size_t bytes = sizeof(double) * (size_t)TOTAL;
+};
 
-  const FcPlanDev& fc = a.fc;
-  const int n = fc.n, d = fc.d, C = fc.C, E = fc.E;
-  const int lane = threadIdx.x;
-  const int line0 = 2 * remap_pair(blockIdx.x);
-  if (line0 >= a.nlines) return;
-  const bool has1 = line0 + 1 < a.nlines;
-  const int g = blockIdx.y, q = blockIdx.z;
-  const int64_t base0 = (int64_t)q * a.inst_stride + (int64_t)g * a.grp_stride + (int64_t)line0 * a.line_stride;
-  const int s0 = g * kGroup;
-  auto ph = [](int i) { return (i / N2) * PS + i % N2; };
-
+template <typename T, int TMAX, int N1, int N2>
+__device__ __forceinline__ void stage_unit(const UnitRegs<T, TMAX>& R, const UnitDesc& d, const double* coef,
+                                           bool adj, int n, int lane, cx<double>* buf) {
+  constexpr int N = N1 * N2, PS = N2 + 1, LSZ = N1 * PS;
   double cf[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) cf[r] = adj ? a.coef[s0 + r] : 1.0;
-
-  // ---- load two lines x four slots as four complex lines
-  for (int e = lane; e < 2 * n; e += 64) {
-    const int it = e & 1, i = e >> 1;
-    cx<double> z0 = {0.0, 0.0}, z1 = {0.0, 0.0};
-    if (it == 0 || has1) {
-      const T* p = a.in + base0 + it * a.line_stride + (int64_t)i * a.pt_stride;
-      z0 = {cf[0] * (double)p[0], cf[1] * (double)p[1]};
-      z1 = {cf[2] * (double)p[2], cf[3] * (double)p[3]};
+  for (int r = 0; r < 4; ++r) cf[r] = adj ? coef[d.s0 + r] : 1.0;
+#pragma unroll
+  for (int t = 0; t < TMAX; ++t) {
+    const int e = lane + 64 * t, it = e & 1, i = e >> 1;
+    if (i < n) {
+      const int ph = (i / N2) * PS + i % N2;
+      buf[(2 * it) * LSZ + ph] = {cf[0] * (double)R.v[t][0], cf[1] * (double)R.v[t][1]};
+      buf[(2 * it + 1) * LSZ + ph] = {cf[2] * (double)R.v[t][2], cf[3] * (double)R.v[t][3]};
     }
-    buf[(2 * it) * LSZ + ph(i)] = z0;
-    buf[(2 * it + 1) * LSZ + ph(i)] = z1;
   }
   if (adj) {
     const int ext = N - n;
     for (int e = lane; e < kLP * ext; e += 64) {
       const int l = e / ext, i = n + e % ext;
-      buf[l * LSZ + ph(i)] = {0.0, 0.0};
+      buf[l * LSZ + (i / N2) * PS + i % N2] = {0.0, 0.0};
     }
   }
-  __syncthreads();
+}
 
-  if (!adj) {
-    // Gram projections (Sec. 4.3 step 1)
-    for (int t = lane; t < kLP * 2 * d; t += 64) {
-      const int l = t / (2 * d), rem = t % (2 * d), end = rem / d, j = rem % d;
+// Continuation, derivative (or its transpose) and store of one staged unit.
+template <typename T, bool ADJ, int TMAX, int N1, int N2>
+__device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int dd, int C, int E,
+                                               int lane, cx<double>* buf, cx<double>* cs, const double* roots,
+                                               const double* mu, const double* Qs, const double* As) {
+  constexpr int N = N1 * N2, PS = N2 + 1, LSZ = N1 * PS;
+  auto ph = [](int i) { return (i / N2) * PS + i % N2; };
+
+  if (!ADJ) {
+    // Gram projections of the matching values (Sec. 4.3 step 1)
+    for (int t = lane; t < kLP * 2 * dd; t += 64) {
+      const int l = t / (2 * dd), rem = t % (2 * dd), end = rem / dd, j = rem % dd;
       double sr = 0, si = 0;
-      for (int k = 0; k < d; ++k) {
-        const double qv = fc.Q[k * d + j];
-        const cx<double> v = buf[l * LSZ + ph(end ? n - d + k : d - 1 - k)];
-        sr += qv * v.re;
-        si += qv * v.im;
+#pragma unroll
+      for (int k = 0; k < kMaxFcD; ++k) {
+        if (k < dd) {
+          const double qv = Qs[k * dd + j];
+          const cx<double> v = buf[l * LSZ + ph(end ? n - dd + k : dd - 1 - k)];
+          sr += qv * v.re;
+          si += qv * v.im;
+        }
       }
       cs[(l * 2 + end) * kMaxFcD + j] = {sr, si};
     }
@@ -106,18 +173,27 @@ __global__ __launch_bounds__(64) void line4_kernel(Line4Args<T> a) {
     for (int t = lane; t < kLP * CE; t += 64) {
       const int l = t / CE, p = t % CE;
       double sr = 0, si = 0;
-      if (p < C)
-        for (int j = 0; j < d; ++j) {
-          const double av = fc.A[p * d + j];
-          sr += av * cs[(l * 2 + 1) * kMaxFcD + j].re;
-          si += av * cs[(l * 2 + 1) * kMaxFcD + j].im;
+      if (p < C) {
+#pragma unroll
+        for (int j = 0; j < kMaxFcD; ++j) {
+          if (j < dd) {
+            const double av = As[p * dd + j];
+            const cx<double> c = cs[(l * 2 + 1) * kMaxFcD + j];
+            sr += av * c.re;
+            si += av * c.im;
+          }
         }
+      }
       if (p >= E) {
         const int pp = CE - 1 - p;
-        for (int j = 0; j < d; ++j) {
-          const double av = fc.A[pp * d + j];
-          sr += av * cs[(l * 2 + 0) * kMaxFcD + j].re;
-          si += av * cs[(l * 2 + 0) * kMaxFcD + j].im;
+#pragma unroll
+        for (int j = 0; j < kMaxFcD; ++j) {
+          if (j < dd) {
+            const double av = As[pp * dd + j];
+            const cx<double> c = cs[(l * 2 + 0) * kMaxFcD + j];
+            sr += av * c.re;
+            si += av * c.im;
+          }
         }
       }
       buf[l * LSZ + ph(n + p)] = {sr, si};
@@ -125,9 +201,7 @@ __global__ __launch_bounds__(64) void line4_kernel(Line4Args<T> a) {
     __syncthreads();
   }
 
-  const double* __restrict__ roots = fc.roots;
-  const double* __restrict__ mu = fc.mu;
-  // ---- step A: length-N1 transforms along the stride-N2 index
+  // step A: length-N1 transforms along the stride-N2 index
   for (int job = lane; job < kLP * N2; job += 64) {
     const int l = job / N2, n2 = job % N2;
     cx<double> x[N1];
@@ -143,7 +217,7 @@ __global__ __launch_bounds__(64) void line4_kernel(Line4Args<T> a) {
     for (int i = 0; i < N1; ++i) buf[l * LSZ + i * PS + n2] = x[i];
   }
   __syncthreads();
-  // ---- step B: length-N2 transforms, derivative factor, inverse transforms
+  // step B: length-N2 transforms, derivative factor, inverse transforms
   for (int job = lane; job < kLP * N1; job += 64) {
     const int l = job / N1, k1 = job % N1;
     cx<double> x[N2];
@@ -154,7 +228,7 @@ __global__ __launch_bounds__(64) void line4_kernel(Line4Args<T> a) {
     for (int k2 = 0; k2 < N2; ++k2) {
       const double m = mu[k1 + N1 * k2];
       const cx<double> X = x[k2];
-      x[k2] = adj ? cx<double>{m * X.im, -m * X.re} : cx<double>{-m * X.im, m * X.re};
+      x[k2] = ADJ ? cx<double>{m * X.im, -m * X.re} : cx<double>{-m * X.im, m * X.re};
     }
     Dft<N2, 1, double>::run(x);
 #pragma unroll
@@ -166,7 +240,7 @@ __global__ __launch_bounds__(64) void line4_kernel(Line4Args<T> a) {
     for (int i = 0; i < N2; ++i) buf[l * LSZ + k1 * PS + i] = x[i];
   }
   __syncthreads();
-  // ---- step A': inverse length-N1 transforms
+  // step A': inverse length-N1 transforms
   for (int job = lane; job < kLP * N2; job += 64) {
     const int l = job / N2, n2 = job % N2;
     cx<double> x[N1];
@@ -179,13 +253,14 @@ __global__ __launch_bounds__(64) void line4_kernel(Line4Args<T> a) {
   __syncthreads();
 
   cx<double>* gs = cs + kLP * 2 * kMaxFcD;
-  if (adj) {
+  if (ADJ) {
     // fold the extension region back onto the first and last d points
-    for (int t = lane; t < kLP * 2 * d; t += 64) {
-      const int l = t / (2 * d), rem = t % (2 * d), end = rem / d, j = rem % d;
+    for (int t = lane; t < kLP * 2 * dd; t += 64) {
+      const int l = t / (2 * dd), rem = t % (2 * dd), end = rem / dd, j = rem % dd;
       double sr = 0, si = 0;
+#pragma unroll 5
       for (int p = 0; p < C; ++p) {
-        const double av = fc.A[p * d + j];
+        const double av = As[p * dd + j];
         const cx<double> v = buf[l * LSZ + ph(end ? n + p : N - 1 - p)];
         sr += av * v.re;
         si += av * v.im;
@@ -193,51 +268,195 @@ __global__ __launch_bounds__(64) void line4_kernel(Line4Args<T> a) {
       cs[(l * 2 + end) * kMaxFcD + j] = {sr, si};
     }
     __syncthreads();
-    for (int t = lane; t < kLP * 2 * d; t += 64) {
-      const int l = t / (2 * d), rem = t % (2 * d), end = rem / d, k = rem % d;
+    for (int t = lane; t < kLP * 2 * dd; t += 64) {
+      const int l = t / (2 * dd), rem = t % (2 * dd), end = rem / dd, k = rem % dd;
       double sr = 0, si = 0;
-      for (int j = 0; j < d; ++j) {
-        const double qv = fc.Q[k * d + j];
-        sr += qv * cs[(l * 2 + end) * kMaxFcD + j].re;
-        si += qv * cs[(l * 2 + end) * kMaxFcD + j].im;
+#pragma unroll
+      for (int j = 0; j < kMaxFcD; ++j) {
+        if (j < dd) {
+          const double qv = Qs[k * dd + j];
+          const cx<double> c = cs[(l * 2 + end) * kMaxFcD + j];
+          sr += qv * c.re;
+          si += qv * c.im;
+        }
       }
       gs[(l * 2 + end) * kMaxFcD + k] = {sr, si};
     }
     __syncthreads();
   }
 
-  // ---- epilogue
+  // epilogue: scale (forward) or add the fold (transpose) and store
   double c4[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) c4[r] = a.coef[s0 + r];
-  for (int e = lane; e < 2 * n; e += 64) {
-    const int it = e & 1, i = e >> 1;
-    if (it == 1 && !has1) continue;
-    const cx<double> z0 = buf[(2 * it) * LSZ + ph(i)], z1 = buf[(2 * it + 1) * LSZ + ph(i)];
-    double dv[4] = {z0.re, z0.im, z1.re, z1.im};
-    if (adj) {
-      if (i >= n - d) {
-        const int k = i - (n - d);
-        const cx<double> ga = gs[((2 * it) * 2 + 1) * kMaxFcD + k], gb = gs[((2 * it + 1) * 2 + 1) * kMaxFcD + k];
-        dv[0] += ga.re; dv[1] += ga.im; dv[2] += gb.re; dv[3] += gb.im;
+  for (int r = 0; r < 4; ++r) c4[r] = ADJ ? 1.0 : -a.coef[d.dir][d.s0 + r];
+  T* out = a.out[d.dir] + d.base;
+  const int64_t ls = a.line_stride[d.dir], ps = a.pt_stride[d.dir];
+#pragma unroll
+  for (int t = 0; t < TMAX; ++t) {
+    const int e = lane + 64 * t, it = e & 1, i = e >> 1;
+    if (i < n && (it == 0 || d.has1)) {
+      const cx<double> z0 = buf[(2 * it) * LSZ + ph(i)], z1 = buf[(2 * it + 1) * LSZ + ph(i)];
+      double dv[4] = {z0.re, z0.im, z1.re, z1.im};
+      if (ADJ) {
+        if (i >= n - dd) {
+          const int k = i - (n - dd);
+          const cx<double> ga = gs[((2 * it) * 2 + 1) * kMaxFcD + k], gb = gs[((2 * it + 1) * 2 + 1) * kMaxFcD + k];
+          dv[0] += ga.re; dv[1] += ga.im; dv[2] += gb.re; dv[3] += gb.im;
+        }
+        if (i < dd) {
+          const int k = dd - 1 - i;
+          const cx<double> ga = gs[((2 * it) * 2 + 0) * kMaxFcD + k], gb = gs[((2 * it + 1) * 2 + 0) * kMaxFcD + k];
+          dv[0] += ga.re; dv[1] += ga.im; dv[2] += gb.re; dv[3] += gb.im;
+        }
       }
-      if (i < d) {
-        const int k = d - 1 - i;
-        const cx<double> ga = gs[((2 * it) * 2 + 0) * kMaxFcD + k], gb = gs[((2 * it + 1) * 2 + 0) * kMaxFcD + k];
-        dv[0] += ga.re; dv[1] += ga.im; dv[2] += gb.re; dv[3] += gb.im;
+      T* p = out + it * ls + (int64_t)i * ps;
+      if constexpr (sizeof(T) == 8) {
+        reinterpret_cast<double2*>(p)[0] = make_double2(c4[0] * dv[0], c4[1] * dv[1]);
+        reinterpret_cast<double2*>(p)[1] = make_double2(c4[2] * dv[2], c4[3] * dv[3]);
+      } else {
+        *reinterpret_cast<float4*>(p) =
+            make_float4(float(c4[0] * dv[0]), float(c4[1] * dv[1]), float(c4[2] * dv[2]), float(c4[3] * dv[3]));
       }
     }
-    const int64_t off = base0 + it * a.line_stride + (int64_t)i * a.pt_stride;
-    T o[4];
+  }
+}
+
+// Issue the loads of the FC tables into registers (kept until staged).
+template <int N>
+struct TabRegs {
+  static constexpr int RT = (2 * N + 63) / 64, MT = (N + 63) / 64, QT = kFcTab / 64;
+  double rr[RT], mm[MT], qq[QT];
+  __device__ __forceinline__ void load(const FcPlanDev& fc, int lane) {
+    const int dd = fc.d, nqa = fc.d * fc.d + fc.C * fc.d;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (MODE == LINE_FWD_X) o[r] = T(-c4[r] * dv[r]);
-      else if (MODE == LINE_FWD_Y) o[r] = T((double)a.aux[off + r] - c4[r] * dv[r]);
-      else if (MODE == LINE_ADJ_X) o[r] = T(dv[r]);
-      else o[r] = T((double)a.aux2[off + r] - a.cdt * ((double)a.aux[off + r] + dv[r]));
+    for (int t = 0; t < RT; ++t) {
+      const int k = lane + 64 * t;
+      rr[t] = (k < 2 * N) ? fc.roots[k] : 0.0;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) a.out[off + r] = o[r];
+    for (int t = 0; t < MT; ++t) {
+      const int k = lane + 64 * t;
+      mm[t] = (k < N) ? fc.mu[k] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < QT; ++t) {
+      const int k = lane + 64 * t;
+      qq[t] = (k < dd * dd) ? fc.Q[k] : ((k < nqa) ? fc.A[k - dd * dd] : 0.0);
+    }
+  }
+  __device__ __forceinline__ void stage(double* roots, double* mu, double* qa, int lane) const {
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int k = lane + 64 * t;
+      if (k < 2 * N) roots[k] = rr[t];
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const int k = lane + 64 * t;
+      if (k < N) mu[k] = mm[t];
+    }
+#pragma unroll
+    for (int t = 0; t < QT; ++t) qa[lane + 64 * t] = qq[t];
+  }
+};
+
+// UPW = 2: the wave's two units and the tables are all loaded before the
+// first transform.  UPW = 1 (long lines, whose loads alone would fill the
+// register file): tables first, then the unit in chunks of 8 load slots.
+template <typename T, bool ADJ, int N1, int N2, int UPW>
+__global__ __launch_bounds__(64) void lines4_kernel(Lines4Args<T> a) {
+  constexpr int N = N1 * N2;
+  constexpr int TMAX = (2 * N + 63) / 64;
+  typedef L4Smem<N1, N2> SM;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* sm = reinterpret_cast<double*>(smem_raw);
+  cx<double>* buf = reinterpret_cast<cx<double>*>(sm);
+  cx<double>* cs = reinterpret_cast<cx<double>*>(sm + SM::BUF);
+  double* roots = sm + SM::BUF + SM::CS;
+  double* mu = roots + SM::ROOTS;
+  double* qa = mu + SM::MU;
+
+  const FcPlanDev& fc = a.fc;
+  const int n = fc.n, dd = fc.d, C = fc.C, E = fc.E;
+  const int lane = threadIdx.x;
+  const double* Qs = qa;
+  const double* As = qa + dd * dd;
+
+  if constexpr (UPW == 2) {
+    const UnitDesc d0 = decode_unit(a, 2 * (int)blockIdx.x);
+    const UnitDesc d1 = decode_unit(a, 2 * (int)blockIdx.x + 1);
+    UnitRegs<T, TMAX> R0, R1;
+    load_unit(a, d0, n, lane, R0);
+    load_unit(a, d1, n, lane, R1);
+    TabRegs<N> tab;
+    tab.load(fc, lane);
+    tab.stage(roots, mu, qa, lane);
+    if (d0.live) {
+      stage_unit<T, TMAX, N1, N2>(R0, d0, a.coef[d0.dir], ADJ, n, lane, buf);
+      __syncthreads();
+      transform_unit<T, ADJ, TMAX, N1, N2>(a, d0, n, dd, C, E, lane, buf, cs, roots, mu, Qs, As);
+    }
+    if (d1.live) {
+      __syncthreads();
+      stage_unit<T, TMAX, N1, N2>(R1, d1, a.coef[d1.dir], ADJ, n, lane, buf);
+      __syncthreads();
+      transform_unit<T, ADJ, TMAX, N1, N2>(a, d1, n, dd, C, E, lane, buf, cs, roots, mu, Qs, As);
+    }
+  } else {
+    const UnitDesc d0 = decode_unit(a, (int)blockIdx.x);
+    if (!d0.live) return;
+    {
+      TabRegs<N> tab;
+      tab.load(fc, lane);
+      tab.stage(roots, mu, qa, lane);
+    }
+    constexpr int CH = 8;
+    for (int c0 = 0; c0 < TMAX; c0 += CH) {
+      UnitRegs<T, CH> R;
+      const T* in = a.in + d0.base;
+      const int64_t ls = a.line_stride[d0.dir], ps = a.pt_stride[d0.dir];
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        const int e = lane + 64 * (c0 + t), it = e & 1, i = e >> 1;
+        if (c0 + t < TMAX && i < n && (it == 0 || d0.has1)) {
+          const T* p = in + it * ls + (int64_t)i * ps;
+          if constexpr (sizeof(T) == 8) {
+            const double2 x = reinterpret_cast<const double2*>(p)[0];
+            const double2 y = reinterpret_cast<const double2*>(p)[1];
+            R.v[t][0] = x.x; R.v[t][1] = x.y; R.v[t][2] = y.x; R.v[t][3] = y.y;
+          } else {
+            const float4 x = *reinterpret_cast<const float4*>(p);
+            R.v[t][0] = x.x; R.v[t][1] = x.y; R.v[t][2] = x.z; R.v[t][3] = x.w;
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) R.v[t][r] = T(0);
+        }
+      }
+      const double* cf = a.coef[d0.dir];
+      constexpr int PS = N2 + 1, LSZ = N1 * PS;
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        const int e = lane + 64 * (c0 + t), it = e & 1, i = e >> 1;
+        if (c0 + t < TMAX && i < n) {
+          const int ph = (i / N2) * PS + i % N2;
+          const double f0 = ADJ ? cf[d0.s0] : 1.0, f1 = ADJ ? cf[d0.s0 + 1] : 1.0;
+          const double f2 = ADJ ? cf[d0.s0 + 2] : 1.0, f3 = ADJ ? cf[d0.s0 + 3] : 1.0;
+          buf[(2 * it) * LSZ + ph] = {f0 * (double)R.v[t][0], f1 * (double)R.v[t][1]};
+          buf[(2 * it + 1) * LSZ + ph] = {f2 * (double)R.v[t][2], f3 * (double)R.v[t][3]};
+        }
+      }
+    }
+    if (ADJ) {
+      constexpr int PS = N2 + 1, LSZ = N1 * PS;
+      const int ext = N - n;
+      for (int e = lane; e < kLP * ext; e += 64) {
+        const int l = e / ext, i = n + e % ext;
+        buf[l * LSZ + (i / N2) * PS + i % N2] = {0.0, 0.0};
+      }
+    }
+    __syncthreads();
+    transform_unit<T, ADJ, TMAX, N1, N2>(a, d0, n, dd, C, E, lane, buf, cs, roots, mu, Qs, As);
   }
 }
 
@@ -252,57 +471,60 @@ bool fourstep_split(int Np, int* n1, int* n2) {
   }
 }
 
-template <typename T, int MODE, int N1, int N2>
-static hipError_t go(const Line4Args<T>& a, dim3 grid, hipStream_t s) {
-  const size_t sh = sizeof(cx<double>) * (size_t)(kLP * N1 * (N2 + 1) + 4 * kLP * kMaxFcD);
-  hipLaunchKernelGGL((line4_kernel<T, MODE, N1, N2>), grid, dim3(64), sh, s, a);
+template <typename T, bool ADJ, int N1, int N2>
+static hipError_t go(const Lines4Args<T>& a, hipStream_t s) {
+  if (L4Smem<N1, N2>::bytes > kLines4MaxLds) return hipErrorNotSupported;
+  constexpr int UPW = (2 * N1 * N2 + 63) / 64 <= 9 ? 2 : 1;
+  const int waves = (a.nunits + UPW - 1) / UPW;
+  if (waves == 0) return hipSuccess;
+  const size_t sh = L4Smem<N1, N2>::bytes;
+  hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, UPW>), dim3((unsigned)waves), dim3(64), sh, s, a);
   return hipGetLastError();
 }
 
-template <typename T, int MODE>
-static hipError_t by_size(const Line4Args<T>& a, dim3 grid, hipStream_t s) {
+template <typename T, bool ADJ>
+static hipError_t by_size(const Lines4Args<T>& a, hipStream_t s) {
   switch (a.fc.Np) {
-    case 90: return go<T, MODE, 9, 10>(a, grid, s);
-    case 160: return go<T, MODE, 16, 10>(a, grid, s);
-    case 288: return go<T, MODE, 16, 18>(a, grid, s);
-    case 540: return go<T, MODE, 20, 27>(a, grid, s);
-    case 1080: return go<T, MODE, 30, 36>(a, grid, s);
+    case 90: return go<T, ADJ, 9, 10>(a, s);
+    case 160: return go<T, ADJ, 16, 10>(a, s);
+    case 288: return go<T, ADJ, 16, 18>(a, s);
+    case 540: return go<T, ADJ, 20, 27>(a, s);
+    case 1080: return go<T, ADJ, 30, 36>(a, s);
     default: return hipErrorNotSupported;
   }
 }
 
 template <typename T>
 static hipError_t launch4_t(const Plan& p, const LineLaunch& L, hipStream_t s) {
-  Line4Args<T> a;
+  Lines4Args<T> a;
   a.in = static_cast<const T*>(L.in);
-  a.aux = static_cast<const T*>(L.aux);
-  a.aux2 = static_cast<const T*>(L.aux2);
-  a.out = static_cast<T*>(L.out);
-  a.coef = (L.dir == 0) ? p.dev.xi : p.dev.eta;
-  a.cdt = L.cdt;
-  a.fc = (L.dir == 0) ? p.fcx : p.fcy;
-  a.grp_stride = p.ny * p.nx * kGroup;
-  a.inst_stride = p.G * a.grp_stride;
-  if (L.dir == 0) {
-    a.nlines = (int)p.ny;
-    a.line_stride = p.nx * kGroup;
-    a.pt_stride = kGroup;
-  } else {
-    a.nlines = (int)p.nx;
-    a.line_stride = kGroup;
-    a.pt_stride = p.nx * kGroup;
+  a.out[0] = static_cast<T*>(L.out_x);
+  a.out[1] = static_cast<T*>(L.out_y);
+  a.coef[0] = p.dev.xi;
+  a.coef[1] = p.dev.eta;
+  a.nlines[0] = (int)p.ny;
+  a.nlines[1] = (int)p.nx;
+  a.line_stride[0] = p.nxp * kGroup;
+  a.pt_stride[0] = kGroup;
+  a.line_stride[1] = kGroup;
+  a.pt_stride[1] = p.nxp * kGroup;
+  for (int k = 0; k < 2; ++k) {
+    const int np = (a.nlines[k] + 1) / 2;
+    a.npe[k] = np + (np & 1);
   }
-  const int npairs = (a.nlines + 1) / 2;
-  dim3 grid((unsigned)(((npairs + 15) / 16) * 16), (unsigned)p.G, (unsigned)p.Nq);
-  switch (L.mode) {
-    case LINE_FWD_X: return by_size<T, LINE_FWD_X>(a, grid, s);
-    case LINE_FWD_Y: return by_size<T, LINE_FWD_Y>(a, grid, s);
-    case LINE_ADJ_X: return by_size<T, LINE_ADJ_X>(a, grid, s);
-    default: return by_size<T, LINE_ADJ_Y>(a, grid, s);
-  }
+  a.grp_stride = p.grp_stride;
+  a.inst_stride = p.inst_stride;
+  a.G = (int)p.G;
+  const bool dx = (L.dirs & 1) != 0, dy = (L.dirs & 2) != 0;
+  a.dir_first = dx ? 0 : 1;
+  a.fc = dx ? p.fcx : p.fcy;
+  const int64_t per = p.Nq * p.G;
+  a.units_first = (int)(per * a.npe[a.dir_first]);
+  a.nunits = a.units_first + ((dx && dy) ? (int)(per * a.npe[1]) : 0);
+  return L.mode == LINE_ADJ ? by_size<T, true>(a, s) : by_size<T, false>(a, s);
 }
 
-hipError_t launch_line4(const Plan& p, const LineLaunch& L, hipStream_t s) {
+hipError_t launch_lines4(const Plan& p, const LineLaunch& L, hipStream_t s) {
   if (p.dtype == RTE_F64) return launch4_t<double>(p, L, s);
   return launch4_t<float>(p, L, s);
 }

@@ -3,11 +3,13 @@
 // transpose for the adjoint (Sec. 4.3; Algorithm 1, loops over y_j and x_i).
 //
 // Storage: a state is [q][g][j][i][r] with g = ordinate group (4 slots),
-// r = slot within the group, so a row of one group is contiguous and a
-// column of one group is a run of 32-byte (FP64) chunks.  One workgroup
-// handles one (line, group, source): the 4 slots form two complex lines
-// (slots r0 + i r1 and r2 + i r3), differentiated together since the FC
-// operator is real-linear.
+// r = slot within the group and rows padded to nxp nodes, so a row of one
+// group is contiguous and a column of one group is a run of 32-byte (FP64)
+// chunks.  This generic kernel (any 5-smooth N_p, runtime Stockham passes)
+// serves the lengths without a four-step split.  One workgroup handles one
+// (line, group, source): the 4 slots form two complex lines (slots r0 + i r1
+// and r2 + i r3), differentiated together since the FC operator is
+// real-linear.
 //
 // Forward derivative of a complex line z (n points):
 //   c_R = Q^T z[n-d..n-1], c_L = Q^T rev(z[0..d-1])          (Gram projection)
@@ -24,11 +26,8 @@ namespace rte {
 template <typename T>
 struct LineArgs {
   const T* in;
-  const T* aux;
-  const T* aux2;
   T* out;
   const double* coef;  // xi or eta per slot
-  double cdt;
   FcPlanDev fc;
   int nlines;
   int64_t line_stride, pt_stride, grp_stride, inst_stride;
@@ -44,7 +43,7 @@ __device__ __forceinline__ int remap_line(int b) {
   return chunk * 32 + 4 * x + k;
 }
 
-template <typename T, int MODE>
+template <typename T, bool adj>
 __global__ __launch_bounds__(kLineThreads) void line_kernel(LineArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const FcPlanDev& fc = a.fc;
@@ -67,7 +66,6 @@ __global__ __launch_bounds__(kLineThreads) void line_kernel(LineArgs<T> a) {
 
   const int64_t base = (int64_t)q * a.inst_stride + (int64_t)g * a.grp_stride + (int64_t)line * a.line_stride;
   const T* in = a.in + base;
-  constexpr bool adj = (MODE == LINE_ADJ_X || MODE == LINE_ADJ_Y);
   const int s0 = g * kGroup;
 
   CT cf[4];
@@ -189,14 +187,11 @@ __global__ __launch_bounds__(kLineThreads) void line_kernel(LineArgs<T> a) {
     __syncthreads();
   }
 
-  // ---- epilogue: combine with the other terms and store
-  const double* cof = a.coef;
+  // ---- epilogue: scale (forward) or add the fold (transpose) and store
   CT c4[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) c4[r] = CT(cof[s0 + r]);
+  for (int r = 0; r < 4; ++r) c4[r] = adj ? CT(1) : -CT(a.coef[s0 + r]);
   T* out = a.out + base;
-  const T* aux = a.aux ? a.aux + base : nullptr;
-  const T* aux2 = a.aux2 ? a.aux2 + base : nullptr;
   const cplx<double>* gs = cs + 4 * kMaxFcD;
   for (int i = tid; i < n; i += nthr) {
     const cplx<CT> z0 = src[i], z1 = src[Np + i];
@@ -218,62 +213,63 @@ __global__ __launch_bounds__(kLineThreads) void line_kernel(LineArgs<T> a) {
       }
     }
     const int64_t off = (int64_t)i * a.pt_stride;
-    T o[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (MODE == LINE_FWD_X) o[r] = T(-c4[r] * dv[r]);
-      else if (MODE == LINE_FWD_Y) o[r] = T(CT(aux[off + r]) - c4[r] * dv[r]);
-      else if (MODE == LINE_ADJ_X) o[r] = T(dv[r]);
-      else o[r] = T(CT(aux2[off + r]) - CT(a.cdt) * (CT(aux[off + r]) + dv[r]));
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) out[off + r] = o[r];
+    for (int r = 0; r < 4; ++r) out[off + r] = T(c4[r] * dv[r]);
   }
 }
 
-template <typename T, int MODE>
-static hipError_t launch_mode(const Plan& p, const LineLaunch& L, hipStream_t s) {
+template <typename T, bool adj>
+static hipError_t launch_mode(const Plan& p, const void* in, void* out, int dir, hipStream_t s) {
   LineArgs<T> a;
-  a.in = static_cast<const T*>(L.in);
-  a.aux = static_cast<const T*>(L.aux);
-  a.aux2 = static_cast<const T*>(L.aux2);
-  a.out = static_cast<T*>(L.out);
-  a.coef = (L.dir == 0) ? p.dev.xi : p.dev.eta;
-  a.cdt = L.cdt;
-  a.fc = (L.dir == 0) ? p.fcx : p.fcy;
-  a.grp_stride = p.ny * p.nx * kGroup;
-  a.inst_stride = p.G * a.grp_stride;
-  if (L.dir == 0) {
+  a.in = static_cast<const T*>(in);
+  a.out = static_cast<T*>(out);
+  a.coef = (dir == 0) ? p.dev.xi : p.dev.eta;
+  a.fc = (dir == 0) ? p.fcx : p.fcy;
+  a.grp_stride = p.grp_stride;
+  a.inst_stride = p.inst_stride;
+  if (dir == 0) {
     a.nlines = (int)p.ny;
-    a.line_stride = p.nx * kGroup;
+    a.line_stride = p.nxp * kGroup;
     a.pt_stride = kGroup;
   } else {
     a.nlines = (int)p.nx;
     a.line_stride = kGroup;
-    a.pt_stride = p.nx * kGroup;
+    a.pt_stride = p.nxp * kGroup;
   }
   const int Np = a.fc.Np;
   const size_t shmem = line_shmem_bytes(Np, p.dtype);
   dim3 grid((unsigned)(((a.nlines + 31) / 32) * 32), (unsigned)p.G, (unsigned)p.Nq);
-  hipLaunchKernelGGL((line_kernel<T, MODE>), grid, dim3(kLineThreads), shmem, s, a);
+  hipLaunchKernelGGL((line_kernel<T, adj>), grid, dim3(kLineThreads), shmem, s, a);
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_t(const Plan& p, const LineLaunch& L, hipStream_t s) {
-  switch (L.mode) {
-    case LINE_FWD_X: return launch_mode<T, LINE_FWD_X>(p, L, s);
-    case LINE_FWD_Y: return launch_mode<T, LINE_FWD_Y>(p, L, s);
-    case LINE_ADJ_X: return launch_mode<T, LINE_ADJ_X>(p, L, s);
-    default: return launch_mode<T, LINE_ADJ_Y>(p, L, s);
-  }
+hipError_t launch_line_generic(const Plan& p, const void* in, void* out, int mode, int dir, hipStream_t s) {
+  if (p.dtype == RTE_F64)
+    return mode == LINE_ADJ ? launch_mode<double, true>(p, in, out, dir, s) : launch_mode<double, false>(p, in, out, dir, s);
+  return mode == LINE_ADJ ? launch_mode<float, true>(p, in, out, dir, s) : launch_mode<float, false>(p, in, out, dir, s);
 }
 
-hipError_t launch_line(const Plan& p, const LineLaunch& L, hipStream_t s) {
-  const FcPlanDev& fc = (L.dir == 0) ? p.fcx : p.fcy;
-  if (fc.n1 > 0) return launch_line4(p, L, s);
-  if (p.dtype == RTE_F64) return launch_t<double>(p, L, s);
-  return launch_t<float>(p, L, s);
+// Both line sets: one four-step launch when the x and y plans coincide,
+// otherwise one launch per direction (four-step where N_p has a split).
+hipError_t launch_lines(const Plan& p, const LineLaunch& L, hipStream_t s) {
+  const bool four_x = p.fcx.n1 > 0, four_y = p.fcy.n1 > 0;
+  if (L.dirs == 3 && p.fc_same && four_x) {
+    const hipError_t e = launch_lines4(p, L, s);
+    if (e != hipErrorNotSupported) return e;
+  }
+  for (int dir = 0; dir < 2; ++dir) {
+    if (!(L.dirs & (1 << dir))) continue;
+    void* out = dir == 0 ? L.out_x : L.out_y;
+    hipError_t e = hipErrorNotSupported;
+    if (dir == 0 ? four_x : four_y) {
+      LineLaunch one = L;
+      one.dirs = 1 << dir;
+      e = launch_lines4(p, one, s);
+    }
+    if (e == hipErrorNotSupported) e = launch_line_generic(p, L.in, out, L.mode, dir, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Static LDS limit check used by the plan (bytes of dynamic shared memory).

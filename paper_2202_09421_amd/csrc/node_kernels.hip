@@ -5,17 +5,19 @@
 // and "impose boundary conditions"): for a tile of nodes with all M ordinates,
 //   S    = W u                       HG scattering, a dense M x M contraction
 //                                    per node, on FP64/FP32 MFMA 16x16x4
-//   L^n  = b S - (a + b) u + T       T = -xi Dx u - eta Dy u from the line passes
+//   L^n  = b S - (a + b) u + X + Y   X = -xi Dx u, Y = -eta Dy u from the line passes
 //   u~   = u + c dt (chi0 L^n + chi1 L^{n-1} + chi2 L^{n-2} + chi3 L^{n-3})
 //   u^{n+1} = f u~(reflected slot) + q(x_b, t_{n+1}) on incoming boundary
 //             entries (eq. RTE, last line), u~ elsewhere
 //   flux[w][pos] = sum_m kappa_w(m) u^{n+1}_m on boundary nodes (eq. OpMed)
 //
 // Adjoint node pass (exact transpose, reverse time): with v^k = P^T ubar^k,
+//   ubar^{n+1} = P1^{n+1} - c dt (Dx^T(xi w^{n+1}) + Dy^T(eta w^{n+1}))
+//   v^{n+1} = P^T ubar^{n+1}
 //   w^n  = sum_l chi_l v^{n+1+l}
-//   P1   = v^{n+1} + c dt (b W w - (a + b) w) + D_e^T Gbar^n
+//   P1^n = v^{n+1} + c dt (b W w - (a + b) w) + D_e^T Gbar^n
 //   dJ/da += -c dt sum_m u^n_m w_m,   dJ/db += c dt sum_m u^n_m ((W w)_m - w_m)
-// The line passes then add -c dt (Dx^T(xi w) + Dy^T(eta w)) to P1.
+// The line passes of the same step then form the transposed derivatives of w^n.
 #include <algorithm>
 
 #include "rte_internal.h"
@@ -38,7 +40,6 @@ struct Mfma<double> {
   static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
 };
 template <>
 struct Mfma<float> {
@@ -46,11 +47,24 @@ struct Mfma<float> {
   static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
 };
 
+// Tiling.  A wave owns a 16-node tile (16 consecutive positions of the
+// row-padded layout) and one row tile of 16 output slots (4 ordinate groups);
+// lane l holds node l % 16, slot r = l / 16 of each of its 4 groups, so every
+// global access of a wave is a contiguous 512-byte run per group.  The
+// scattering D[s][node] = sum_s' Wt[s'][s] X[s'][node] is a 16 x 16 x Mpad
+// MFMA product per wave: the A operand is the wave's slice of the HG matrix
+// (kept in registers), the B operand (X at all slots of the tile) is
+// exchanged through LDS among the RT waves that share the tile, and the
+// result lands in exactly the (node, slot) registers of the lane that owns
+// it (for FP32 the rows of the A operand are permuted to make it so).
+// Boundary coupling only mixes slots of one group (the groups are
+// reflection orbits), i.e. the 4 lanes of one node, and uses wave shuffles.
+// NT tiles x RT row tiles per block; RTC = RT at compile time (1..4) or 0
+// for RT >= 5 (NT = 1).
 struct NodeGeom {
-  int nx, ny, M, Mpad, G, nb, npos, K1;
+  int nx, ny, nxp, M, Mpad, G, nb, npos, K1, RT, NT, npos_total;
   int64_t grp_stride, inst_stride;
 };
 
@@ -67,65 +81,62 @@ __device__ __forceinline__ int boundary_pos(int j, int i, int nx, int ny) {
   return 2 * nx + (ny - 2) + j - 1;
 }
 
-// S[node][s] = sum_s' X[node][s'] W[s'][s] for TN nodes; X and S in LDS with
-// row stride LS.  16x16x4 MFMA: A = 16 nodes x 4 slots, B = 4 slots x 16 slots.
-template <typename T, int TN>
-__device__ __forceinline__ void scatter_mfma(const T* X, T* S, int LS, const double* __restrict__ Wt, int Mpad) {
-  typedef typename Mfma<T>::acc_t acc_t;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  constexpr int RB = TN / 16;            // row blocks
-  constexpr int WPR = 4 / RB;            // waves sharing a row block
-  const int rb = wave % RB;
-  const int row = 16 * rb + (lane & 15);
-  const int kq = lane >> 4;
-  const int ntile = Mpad / 16;
-  for (int t = wave / RB; t < ntile; t += WPR) {
-    acc_t acc = {0, 0, 0, 0};
-    for (int kc = 0; kc < Mpad / 4; ++kc) {
-      const T av = X[row * LS + 4 * kc + kq];
-      const T bv = T(Wt[(4 * kc + kq) * Mpad + 16 * t + (lane & 15)]);
-      acc = Mfma<T>::step(av, bv, acc);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) S[(16 * rb + Mfma<T>::row(kq, v)) * LS + 16 * t + (lane & 15)] = acc[v];
-  }
+template <typename T>
+__device__ __forceinline__ int a_row_slot(int rho) {
+  return sizeof(T) == 8 ? rho : 4 * (rho & 3) + (rho >> 2);
 }
 
-// One node's four slots of one ordinate group: 32 bytes (FP64) or 16 (FP32),
-// aligned, moved with vector loads.
-template <typename T>
-struct Quad {
-  T v[4];
+struct TileLane {
+  int node, r, rt, nt, P, j, i;
+  bool valid, bnd;
 };
 
-template <typename T>
-__device__ __forceinline__ Quad<T> ldq(const T* p) {
-  Quad<T> q;
-  if constexpr (sizeof(T) == 8) {
-    const double2 x = reinterpret_cast<const double2*>(p)[0];
-    const double2 y = reinterpret_cast<const double2*>(p)[1];
-    q.v[0] = x.x; q.v[1] = x.y; q.v[2] = y.x; q.v[3] = y.y;
-  } else {
-    const float4 x = *reinterpret_cast<const float4*>(p);
-    q.v[0] = x.x; q.v[1] = x.y; q.v[2] = x.z; q.v[3] = x.w;
-  }
-  return q;
+__device__ __forceinline__ TileLane tile_lane(const NodeGeom& G) {
+  TileLane t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  t.node = lane & 15;
+  t.r = lane >> 4;
+  t.rt = wave % G.RT;
+  t.nt = wave / G.RT;
+  t.P = ((int)blockIdx.x * G.NT + t.nt) * 16 + t.node;
+  t.j = t.P / G.nxp;
+  t.i = t.P - t.j * G.nxp;
+  t.valid = (t.P < G.npos_total) && (t.i < G.nx);
+  t.bnd = t.valid && (t.i == 0 || t.i == G.nx - 1 || t.j == 0 || t.j == G.ny - 1);
+  return t;
 }
 
-template <typename T>
-__device__ __forceinline__ void stq(T* p, const Quad<T>& q) {
-  if constexpr (sizeof(T) == 8) {
-    reinterpret_cast<double2*>(p)[0] = make_double2(q.v[0], q.v[1]);
-    reinterpret_cast<double2*>(p)[1] = make_double2(q.v[2], q.v[3]);
+// MFMA product for the wave's row tile: B operand from the LDS tile Bs
+// ([Mpad][16] of this tile), A fragments af (preloaded) or read from Wt.
+template <typename T, int RTC>
+__device__ __forceinline__ typename Mfma<T>::acc_t scatter_tile(const T* Bs, const T* af, const double* __restrict__ Wt,
+                                                               const NodeGeom& G, const TileLane& t) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  acc_t acc = {0, 0, 0, 0};
+  if constexpr (RTC > 0) {
+#pragma unroll
+    for (int ks = 0; ks < 4 * RTC; ++ks) acc = Mfma<T>::step(af[ks], Bs[(4 * ks + t.r) * 16 + t.node], acc);
   } else {
-    *reinterpret_cast<float4*>(p) = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
+    const int col = 16 * t.rt + a_row_slot<T>(t.node);
+    for (int ks = 0; ks < 4 * G.RT; ++ks)
+      acc = Mfma<T>::step(T(Wt[(4 * ks + t.r) * G.Mpad + col]), Bs[(4 * ks + t.r) * 16 + t.node], acc);
+  }
+  return acc;
+}
+
+template <typename T, int RTC>
+__device__ __forceinline__ void load_afrag(T* af, const double* __restrict__ Wt, const NodeGeom& G, const TileLane& t) {
+  if constexpr (RTC > 0) {
+    const int col = 16 * t.rt + a_row_slot<T>(t.node);
+#pragma unroll
+    for (int ks = 0; ks < 4 * RTC; ++ks) af[ks] = T(Wt[(4 * ks + t.r) * G.Mpad + col]);
   }
 }
 
 // ---------------------------------------------------------------- forward
 template <typename T>
 struct NodeFwdArgs {
-  const T* u; const T* Tt; const T* L1; const T* L2; const T* L3;
+  const T* u; const T* X; const T* Y; const T* L1; const T* L2; const T* L3;
   const T* mu_a; const T* mu_s;
   T* u_out; T* L_out; double* flux;
   const double* Wt; const BcRule* bc; const double* kappa;
@@ -135,307 +146,268 @@ struct NodeFwdArgs {
   double cdt;
 };
 
-// Thread layout: quad index qd = g * TN + nd (group-major, so a wave reads
-// contiguous 2 KB runs); each thread owns QPT quads.  All global loads of a
-// step are issued before the first barrier and stay in registers, so their
-// latency overlaps the MFMA phase.  (L_out aliases L3 by design: every quad
-// is read before it is written, by the same thread.)
-template <typename T, int TN, int QPT>
-__global__ __launch_bounds__(kNodeThreads) void node_fwd_kernel(NodeFwdArgs<T> a) {
+// L_out may alias L3: each element is read and then written by one lane.
+template <typename T, int RTC>
+__global__ __launch_bounds__(RTC == 0 ? 1024 : (RTC == 3 ? 192 : 256)) void node_fwd_kernel(NodeFwdArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const NodeGeom& G = a.geo;
-  const int LS = G.Mpad + 1;
-  T* Us = reinterpret_cast<T*>(smem_raw);
-  T* Ss = Us + TN * LS;
-  T* As = Ss + TN * LS;
-  T* Bs = As + TN;
-  const int tid = threadIdx.x;
+  const TileLane t = tile_lane(G);
+  T* Bs = reinterpret_cast<T*>(smem_raw) + (size_t)t.nt * G.Mpad * 16;
+  double* Fx = reinterpret_cast<double*>(smem_raw + ((sizeof(T) * (size_t)G.NT * G.Mpad * 16 + 15) & ~size_t(15)));
   const int q = blockIdx.y;
-  const int Nn = G.nx * G.ny;
-  const int node0 = blockIdx.x * TN;
   const int64_t ib = (int64_t)q * G.inst_stride;
-  const int nq = G.G * TN;
 
-  Quad<T> tq[QPT], l1[QPT], l2[QPT], l3[QPT];
-  int gq[QPT], nq_[QPT];
-  bool ok[QPT];
+  T u[4], X[4], Y[4], L1[4], L2[4], L3[4];
+  int64_t off[4];
+  bool gv[4];
 #pragma unroll
-  for (int k = 0; k < QPT; ++k) {
-    const int qd = tid + k * kNodeThreads;
-    const int g = qd / TN, nd = qd - g * TN;
-    const int gn = node0 + nd;
-    gq[k] = g;
-    nq_[k] = nd;
-    ok[k] = (qd < nq) && (gn < Nn);
-    Quad<T> u = {{T(0), T(0), T(0), T(0)}};
-    if (ok[k]) {
-      const int64_t off = ib + g * G.grp_stride + (int64_t)gn * kGroup;
-      u = ldq(a.u + off);
-      tq[k] = ldq(a.Tt + off);
-      l1[k] = ldq(a.L1 + off);
-      l2[k] = ldq(a.L2 + off);
-      l3[k] = ldq(a.L3 + off);
-    }
-    if (qd < nq) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Us[nd * LS + g * kGroup + r] = u.v[r];
+  for (int v = 0; v < 4; ++v) {
+    const int g = 4 * t.rt + v;
+    gv[v] = t.valid && g < G.G;
+    off[v] = ib + (int64_t)g * G.grp_stride + (int64_t)t.P * kGroup + t.r;
+    u[v] = X[v] = Y[v] = L1[v] = L2[v] = L3[v] = T(0);
+    if (gv[v]) {
+      u[v] = a.u[off[v]]; X[v] = a.X[off[v]]; Y[v] = a.Y[off[v]];
+      L1[v] = a.L1[off[v]]; L2[v] = a.L2[off[v]]; L3[v] = a.L3[off[v]];
     }
   }
-  for (int e = tid; e < TN * (G.Mpad - G.M); e += kNodeThreads) {
-    const int nd = e / (G.Mpad - G.M), s = G.M + e % (G.Mpad - G.M);
-    Us[nd * LS + s] = T(0);
-  }
-  for (int nd = tid; nd < TN; nd += kNodeThreads) {
-    const int gn = node0 + nd;
-    As[nd] = (gn < Nn) ? a.mu_a[gn] : T(0);
-    Bs[nd] = (gn < Nn) ? a.mu_s[gn] : T(0);
-  }
-  __syncthreads();
+  const int gn = t.j * G.nx + t.i;
+  const T A = t.valid ? a.mu_a[gn] : T(0), B = t.valid ? a.mu_s[gn] : T(0);
+  T af[RTC > 0 ? 4 * RTC : 1];
+  load_afrag<T, RTC>(af, a.Wt, G, t);
 
-  scatter_mfma<T, TN>(Us, Ss, LS, a.Wt, G.Mpad);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Bs[(4 * (4 * t.rt + v) + t.r) * 16 + t.node] = u[v];
   __syncthreads();
+  const typename Mfma<T>::acc_t S = scatter_tile<T, RTC>(Bs, af, a.Wt, G, t);
 
   // L^n and the AB4 combination
   const T cdt = T(a.cdt);
+  T un[4];
 #pragma unroll
-  for (int k = 0; k < QPT; ++k) {
-    if (!ok[k]) continue;
-    const int g = gq[k], nd = nq_[k], gn = node0 + nd;
-    const T A = As[nd], B = Bs[nd];
-    Quad<T> Lq;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int s = g * kGroup + r;
-      const T uu = Us[nd * LS + s];
-      const T Ln = B * Ss[nd * LS + s] - (A + B) * uu + tq[k].v[r];
-      Lq.v[r] = Ln;
-      Ss[nd * LS + s] = uu + cdt * (T(kChi0) * Ln + T(kChi1) * l1[k].v[r] + T(kChi2) * l2[k].v[r] + T(kChi3) * l3[k].v[r]);
-    }
-    stq(a.L_out + ib + g * G.grp_stride + (int64_t)gn * kGroup, Lq);
+  for (int v = 0; v < 4; ++v) {
+    const T Ln = B * S[v] - (A + B) * u[v] + X[v] + Y[v];
+    un[v] = u[v] + cdt * (T(kChi0) * Ln + T(kChi1) * L1[v] + T(kChi2) * L2[v] + T(kChi3) * L3[v]);
+    if (gv[v]) a.L_out[off[v]] = Ln;
   }
-  __syncthreads();
 
   // inflow condition with Fresnel reflection and the beams at t_{n+1}
+  const bool wave_bnd = __ballot(t.bnd) != 0;
+  if (wave_bnd) {
+    const int ty = t.bnd ? node_type(t.j, t.i, G.nx, G.ny) : 0;
+    const int bp = t.bnd ? boundary_pos(t.j, t.i, G.nx, G.ny) : 0;
 #pragma unroll
-  for (int k = 0; k < QPT; ++k) {
-    if (!ok[k]) continue;
-    const int g = gq[k], nd = nq_[k], gn = node0 + nd;
-    const int j = gn / G.nx, i = gn - j * G.nx;
-    const int ty = node_type(j, i, G.nx, G.ny);
-    Quad<T> o;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int s = g * kGroup + r;
-      T val = Ss[nd * LS + s];
-      if (ty != 0) {
-        const BcRule br = a.bc[ty * G.M + s];
-        if (br.flag) {
-          val = T(br.coef_a) * Ss[nd * LS + br.src_a] + T(br.coef_b) * Ss[nd * LS + br.src_b];
-          const int bp = boundary_pos(j, i, G.nx, G.ny);
-          for (int b = a.beam_off[q]; b < a.beam_off[q + 1]; ++b)
-            val += T(a.beam_sp[(int64_t)b * G.nb + bp] * a.beam_an[b * G.M + s]) * T(a.beam_tt[(int64_t)b * G.K1 + a.step + 1]);
-        }
+    for (int v = 0; v < 4; ++v) {
+      const int s = 4 * (4 * t.rt + v) + t.r;
+      BcRule br;
+      br.flag = 0; br.src_a = s; br.src_b = s; br.pad = 0; br.coef_a = 0.0; br.coef_b = 0.0;
+      if (t.bnd && gv[v]) br = a.bc[ty * G.M + s];
+      const T ta = __shfl(un[v], t.node + 16 * (br.src_a & 3));
+      const T tb = __shfl(un[v], t.node + 16 * (br.src_b & 3));
+      if (br.flag) {
+        T val = T(br.coef_a) * ta + T(br.coef_b) * tb;
+        for (int b = a.beam_off[q]; b < a.beam_off[q + 1]; ++b)
+          val += T(a.beam_sp[(int64_t)b * G.nb + bp] * a.beam_an[b * G.M + s]) * T(a.beam_tt[(int64_t)b * G.K1 + a.step + 1]);
+        un[v] = val;
       }
-      o.v[r] = val;
     }
-    stq(a.u_out + ib + g * G.grp_stride + (int64_t)gn * kGroup, o);
-    if (a.flux) {
+  }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Us[nd * LS + g * kGroup + r] = o.v[r];
-    }
-  }
+  for (int v = 0; v < 4; ++v)
+    if (gv[v]) a.u_out[off[v]] = un[v];
   if (a.flux == nullptr) return;
-  __syncthreads();
 
-  // detector flux on boundary nodes (FP64 accumulation)
-  for (int nd = tid; nd < TN; nd += kNodeThreads) {
-    const int gn = node0 + nd;
-    if (gn >= Nn) continue;
-    const int j = gn / G.nx, i = gn - j * G.nx;
-    int walls[2], nw = 0;
-    if (i == 0) walls[nw++] = 0;
-    if (i == G.nx - 1) walls[nw++] = 1;
-    if (j == 0) walls[nw++] = 2;
-    if (j == G.ny - 1) walls[nw++] = 3;
-    for (int t = 0; t < nw; ++t) {
-      const int w = walls[t];
-      double acc = 0.0;
-      for (int s = 0; s < G.M; ++s) acc += a.kappa[w * G.M + s] * (double)Us[nd * LS + s];
-      const int pos = (w < 2) ? j : i;
-      a.flux[(((int64_t)q * G.K1 + a.step + 1) * 4 + w) * G.npos + pos] = acc;
+  // detector flux on boundary nodes (FP64): lane partial over its 4 groups,
+  // then over the 4 slot lanes of the node, then over the row tiles
+  double pw0 = 0.0, pw1 = 0.0;
+  const int wl0 = !t.bnd ? -1 : ((t.i == 0) ? 0 : ((t.i == G.nx - 1) ? 1 : -1));
+  const int wl1 = !t.bnd ? -1 : ((t.j == 0) ? 2 : ((t.j == G.ny - 1) ? 3 : -1));
+  if (wave_bnd) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int s = 4 * (4 * t.rt + v) + t.r;
+      if (gv[v] && wl0 >= 0) pw0 += a.kappa[wl0 * G.M + s] * (double)un[v];
+      if (gv[v] && wl1 >= 0) pw1 += a.kappa[wl1 * G.M + s] * (double)un[v];
     }
+    pw0 += __shfl_xor(pw0, 16);
+    pw1 += __shfl_xor(pw1, 16);
+    pw0 += __shfl_xor(pw0, 32);
+    pw1 += __shfl_xor(pw1, 32);
   }
+  if (G.RT > 1) {
+    if (t.r == 0) {
+      Fx[((t.nt * G.RT + t.rt) * 16 + t.node) * 2 + 0] = pw0;
+      Fx[((t.nt * G.RT + t.rt) * 16 + t.node) * 2 + 1] = pw1;
+    }
+    __syncthreads();
+    if (t.rt != 0 || !t.bnd || t.r != 0) return;
+    pw0 = pw1 = 0.0;
+    for (int k = 0; k < G.RT; ++k) {
+      pw0 += Fx[((t.nt * G.RT + k) * 16 + t.node) * 2 + 0];
+      pw1 += Fx[((t.nt * G.RT + k) * 16 + t.node) * 2 + 1];
+    }
+  } else if (!t.bnd || t.r != 0) {
+    return;
+  }
+  const int64_t fb = ((int64_t)q * G.K1 + a.step + 1) * 4;
+  if (wl0 >= 0) a.flux[(fb + wl0) * G.npos + t.j] = pw0;
+  if (wl1 >= 0) a.flux[(fb + wl1) * G.npos + t.i] = pw1;
 }
 
 // ---------------------------------------------------------------- adjoint
 template <typename T>
 struct NodeAdjArgs {
-  T* v1; const T* v2; const T* v3; const T* v4; const T* u;
+  const T* atx; const T* aty; T* ap1; T* v1_out;
+  const T* v2; const T* v3; const T* v4; const T* u;
   const T* mu_a; const T* mu_s; const double* inj;
-  T* w_out; T* p_out; double* ga; double* gb;
+  T* w_out; double* ga; double* gb;
   const double* Wt; const BcRuleT* bct; const double* kappa;
   NodeGeom geo;
   int step;
-  int convert_v1;
   double cdt;
 };
 
-template <typename T, int TN, int QPT>
-__global__ __launch_bounds__(kNodeThreads) void node_adj_kernel(NodeAdjArgs<T> a) {
+// ap1 is read (P1^{n+1}) and overwritten (P1^n) element by element by one lane.
+template <typename T, int RTC>
+__global__ __launch_bounds__(RTC == 0 ? 1024 : (RTC == 3 ? 192 : 256)) void node_adj_kernel(NodeAdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const NodeGeom& G = a.geo;
-  const int LS = G.Mpad + 1;
-  T* Vb = reinterpret_cast<T*>(smem_raw);
-  T* Wb = Vb + TN * LS;
-  T* Sb = Wb + TN * LS;
-  T* As = Sb + TN * LS;
-  T* Bs = As + TN;
-  // [TN][G] gradient partials, 8-byte aligned after the T arrays
-  double* Pa = reinterpret_cast<double*>(smem_raw + ((sizeof(T) * (size_t)(3 * TN * LS + 2 * TN) + 7) & ~size_t(7)));
-  double* Pb = Pa + TN * G.G;
-  const int tid = threadIdx.x;
+  const TileLane t = tile_lane(G);
+  T* Bs = reinterpret_cast<T*>(smem_raw) + (size_t)t.nt * G.Mpad * 16;
+  double* Fx = reinterpret_cast<double*>(smem_raw + ((sizeof(T) * (size_t)G.NT * G.Mpad * 16 + 15) & ~size_t(15)));
   const int q = blockIdx.y;
-  const int Nn = G.nx * G.ny;
-  const int node0 = blockIdx.x * TN;
   const int64_t ib = (int64_t)q * G.inst_stride;
-  const int nq = G.G * TN;
+  const int Nn = G.nx * G.ny;
 
-  Quad<T> v1[QPT], v2[QPT], v3[QPT], v4[QPT], uq[QPT];
-  int gq[QPT], ndq[QPT];
-  bool ok[QPT];
+  T tx[4], ty[4], p1[4], v2[4], v3[4], v4[4], uu[4];
+  int64_t off[4];
+  bool gv[4];
 #pragma unroll
-  for (int k = 0; k < QPT; ++k) {
-    const int qd = tid + k * kNodeThreads;
-    const int g = qd / TN, nd = qd - g * TN;
-    const int gn = node0 + nd;
-    gq[k] = g;
-    ndq[k] = nd;
-    ok[k] = (qd < nq) && (gn < Nn);
-    Quad<T> z = {{T(0), T(0), T(0), T(0)}};
-    v1[k] = z;
-    if (ok[k]) {
-      const int64_t off = ib + g * G.grp_stride + (int64_t)gn * kGroup;
-      v1[k] = ldq(a.v1 + off);
-      v2[k] = ldq(a.v2 + off);
-      v3[k] = ldq(a.v3 + off);
-      v4[k] = ldq(a.v4 + off);
-      uq[k] = ldq(a.u + off);
-    }
-    if (qd < nq) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Vb[nd * LS + g * kGroup + r] = v1[k].v[r];
+  for (int v = 0; v < 4; ++v) {
+    const int g = 4 * t.rt + v;
+    gv[v] = t.valid && g < G.G;
+    off[v] = ib + (int64_t)g * G.grp_stride + (int64_t)t.P * kGroup + t.r;
+    tx[v] = ty[v] = p1[v] = v2[v] = v3[v] = v4[v] = uu[v] = T(0);
+    if (gv[v]) {
+      tx[v] = a.atx[off[v]]; ty[v] = a.aty[off[v]]; p1[v] = a.ap1[off[v]];
+      v2[v] = a.v2[off[v]]; v3[v] = a.v3[off[v]]; v4[v] = a.v4[off[v]];
+      uu[v] = a.u[off[v]];
     }
   }
-  for (int nd = tid; nd < TN; nd += kNodeThreads) {
-    const int gn = node0 + nd;
-    As[nd] = (gn < Nn) ? a.mu_a[gn] : T(0);
-    Bs[nd] = (gn < Nn) ? a.mu_s[gn] : T(0);
-  }
-  for (int e = tid; e < TN * (G.Mpad - G.M); e += kNodeThreads) {
-    const int nd = e / (G.Mpad - G.M), s = G.M + e % (G.Mpad - G.M);
-    Wb[nd * LS + s] = T(0);
-  }
-  __syncthreads();
+  const int gn = t.j * G.nx + t.i;
+  const T A = t.valid ? a.mu_a[gn] : T(0), B = t.valid ? a.mu_s[gn] : T(0);
+  T af[RTC > 0 ? 4 * RTC : 1];
+  load_afrag<T, RTC>(af, a.Wt, G, t);
 
-  // v^{n+1} = P^T ubar^{n+1} on boundary nodes, w^n in registers and LDS
+  // ubar^{n+1}, then v^{n+1} = P^T ubar^{n+1} on boundary nodes
+  const double cdt = a.cdt;
+  T v1[4];
 #pragma unroll
-  for (int k = 0; k < QPT; ++k) {
-    if (!ok[k]) continue;
-    const int g = gq[k], nd = ndq[k], gn = node0 + nd;
-    if (a.convert_v1) {
-      const int j = gn / G.nx, i = gn - j * G.nx;
-      const int ty = node_type(j, i, G.nx, G.ny);
-      if (ty != 0) {
-        Quad<T> c;
+  for (int v = 0; v < 4; ++v) v1[v] = T((double)p1[v] - cdt * ((double)tx[v] + (double)ty[v]));
+  const bool wave_bnd = __ballot(t.bnd) != 0;
+  if (wave_bnd) {
+    const int tyn = t.bnd ? node_type(t.j, t.i, G.nx, G.ny) : 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const BcRuleT rt = a.bct[ty * G.M + g * kGroup + r];
-          T val = rt.is_target ? T(0) : v1[k].v[r];
-          for (int t = 0; t < rt.ntgt; ++t) val += T(rt.coef[t]) * Vb[nd * LS + rt.tgt[t]];
-          c.v[r] = val;
-        }
-        v1[k] = c;
-        stq(a.v1 + ib + g * G.grp_stride + (int64_t)gn * kGroup, c);
+    for (int v = 0; v < 4; ++v) {
+      const int s = 4 * (4 * t.rt + v) + t.r;
+      BcRuleT rt;
+      rt.is_target = 0; rt.ntgt = 0; rt.tgt[0] = s; rt.tgt[1] = s; rt.coef[0] = 0.0; rt.coef[1] = 0.0;
+      if (t.bnd && gv[v]) rt = a.bct[tyn * G.M + s];
+      const T t0 = __shfl(v1[v], t.node + 16 * (rt.tgt[0] & 3));
+      const T t1 = __shfl(v1[v], t.node + 16 * (rt.tgt[1] & 3));
+      if (t.bnd && gv[v]) {
+        T val = rt.is_target ? T(0) : v1[v];
+        if (rt.ntgt > 0) val += T(rt.coef[0]) * t0;
+        if (rt.ntgt > 1) val += T(rt.coef[1]) * t1;
+        v1[v] = val;
       }
     }
+  }
+
+  // w^n, and W w on the MFMA
+  T w[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      Wb[nd * LS + g * kGroup + r] =
-          T(kChi0) * v1[k].v[r] + T(kChi1) * v2[k].v[r] + T(kChi2) * v3[k].v[r] + T(kChi3) * v4[k].v[r];
+  for (int v = 0; v < 4; ++v) {
+    w[v] = T(kChi0) * v1[v] + T(kChi1) * v2[v] + T(kChi2) * v3[v] + T(kChi3) * v4[v];
+    Bs[(4 * (4 * t.rt + v) + t.r) * 16 + t.node] = w[v];
   }
   __syncthreads();
+  const typename Mfma<T>::acc_t S = scatter_tile<T, RTC>(Bs, af, a.Wt, G, t);
 
-  scatter_mfma<T, TN>(Wb, Sb, LS, a.Wt, G.Mpad);
-  __syncthreads();
-
-  // P1, w and the gradient products
-  const T cdt = T(a.cdt);
+  // P1^n, stores and the gradient products
+  const T cdtT = T(cdt);
+  double pa = 0.0, pb = 0.0;
+  const int64_t ib4 = ((int64_t)q * G.K1 + a.step) * 4;
 #pragma unroll
-  for (int k = 0; k < QPT; ++k) {
-    if (!ok[k]) continue;
-    const int g = gq[k], nd = ndq[k], gn = node0 + nd;
-    const int j = gn / G.nx, i = gn - j * G.nx;
-    const bool bnd = node_type(j, i, G.nx, G.ny) != 0;
-    const T A = As[nd], B = Bs[nd];
-    Quad<T> p1, wq;
-    double pa = 0.0, pb = 0.0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int s = g * kGroup + r;
-      const T w = Wb[nd * LS + s], S = Sb[nd * LS + s];
-      T p = v1[k].v[r] + cdt * (B * S - (A + B) * w);
-      if (bnd) {
-        // detector misfit enters through the outgoing boundary entries
-        const int64_t ib4 = ((int64_t)q * G.K1 + a.step) * 4;
-        if (i == 0) p += T(a.kappa[0 * G.M + s] * a.inj[(ib4 + 0) * G.npos + j]);
-        if (i == G.nx - 1) p += T(a.kappa[1 * G.M + s] * a.inj[(ib4 + 1) * G.npos + j]);
-        if (j == 0) p += T(a.kappa[2 * G.M + s] * a.inj[(ib4 + 2) * G.npos + i]);
-        if (j == G.ny - 1) p += T(a.kappa[3 * G.M + s] * a.inj[(ib4 + 3) * G.npos + i]);
-      }
-      p1.v[r] = p;
-      wq.v[r] = w;
-      pa += (double)uq[k].v[r] * (double)w;
-      pb += (double)uq[k].v[r] * ((double)S - (double)w);
+  for (int v = 0; v < 4; ++v) {
+    const int s = 4 * (4 * t.rt + v) + t.r;
+    T p = v1[v] + cdtT * (B * S[v] - (A + B) * w[v]);
+    if (t.bnd && gv[v]) {
+      // detector misfit enters through the outgoing boundary entries
+      if (t.i == 0) p += T(a.kappa[0 * G.M + s] * a.inj[(ib4 + 0) * G.npos + t.j]);
+      if (t.i == G.nx - 1) p += T(a.kappa[1 * G.M + s] * a.inj[(ib4 + 1) * G.npos + t.j]);
+      if (t.j == 0) p += T(a.kappa[2 * G.M + s] * a.inj[(ib4 + 2) * G.npos + t.i]);
+      if (t.j == G.ny - 1) p += T(a.kappa[3 * G.M + s] * a.inj[(ib4 + 3) * G.npos + t.i]);
     }
-    const int64_t off = ib + g * G.grp_stride + (int64_t)gn * kGroup;
-    stq(a.p_out + off, p1);
-    stq(a.w_out + off, wq);
-    Pa[nd * G.G + g] = pa;
-    Pb[nd * G.G + g] = pb;
-  }
-  __syncthreads();
-
-  // per-node gradient sums over the groups (fixed order: deterministic)
-  for (int nd = tid; nd < TN; nd += kNodeThreads) {
-    const int gn = node0 + nd;
-    if (gn >= Nn) continue;
-    double sa = 0.0, sb = 0.0;
-    for (int g = 0; g < G.G; ++g) {
-      sa += Pa[nd * G.G + g];
-      sb += Pb[nd * G.G + g];
+    if (gv[v]) {
+      a.ap1[off[v]] = p;
+      a.w_out[off[v]] = w[v];
+      a.v1_out[off[v]] = v1[v];
     }
-    a.ga[(int64_t)q * Nn + gn] -= a.cdt * sa;
-    a.gb[(int64_t)q * Nn + gn] += a.cdt * sb;
+    pa += (double)uu[v] * (double)w[v];
+    pb += (double)uu[v] * ((double)S[v] - (double)w[v]);
   }
+  pa += __shfl_xor(pa, 16);
+  pb += __shfl_xor(pb, 16);
+  pa += __shfl_xor(pa, 32);
+  pb += __shfl_xor(pb, 32);
+  if (G.RT > 1) {
+    if (t.r == 0) {
+      Fx[((t.nt * G.RT + t.rt) * 16 + t.node) * 2 + 0] = pa;
+      Fx[((t.nt * G.RT + t.rt) * 16 + t.node) * 2 + 1] = pb;
+    }
+    __syncthreads();
+    if (t.rt != 0 || t.r != 0 || !t.valid) return;
+    pa = pb = 0.0;
+    for (int k = 0; k < G.RT; ++k) {
+      pa += Fx[((t.nt * G.RT + k) * 16 + t.node) * 2 + 0];
+      pb += Fx[((t.nt * G.RT + k) * 16 + t.node) * 2 + 1];
+    }
+  } else if (t.r != 0 || !t.valid) {
+    return;
+  }
+  a.ga[(int64_t)q * Nn + gn] -= cdt * pa;
+  a.gb[(int64_t)q * Nn + gn] += cdt * pb;
 }
 
 // ---------------------------------------------------------------- launchers
 static NodeGeom make_geom(const Plan& p) {
   NodeGeom g;
-  g.nx = (int)p.nx; g.ny = (int)p.ny; g.M = (int)p.M; g.Mpad = (int)p.Mpad; g.G = (int)p.G;
+  g.nx = (int)p.nx; g.ny = (int)p.ny; g.nxp = (int)p.nxp;
+  g.M = (int)p.M; g.Mpad = (int)p.Mpad; g.G = (int)p.G;
   g.nb = (int)p.nb; g.npos = (int)p.npos; g.K1 = (int)(p.K + 1);
-  g.grp_stride = p.ny * p.nx * kGroup;
-  g.inst_stride = p.G * g.grp_stride;
+  g.RT = (int)(p.Mpad / 16);
+  g.NT = (g.RT <= 4 && 4 % g.RT == 0) ? 4 / g.RT : 1;
+  g.npos_total = (int)(p.ny * p.nxp);
+  g.grp_stride = p.grp_stride;
+  g.inst_stride = p.inst_stride;
   return g;
 }
 
-template <typename T>
-static int node_tile(const Plan& p) { return (p.Mpad * sizeof(T) <= 256) ? 64 : 32; }
+static size_t node_shmem(const NodeGeom& g, size_t es) {
+  return ((es * (size_t)g.NT * g.Mpad * 16 + 15) & ~size_t(15)) + sizeof(double) * 2 * (size_t)g.NT * g.RT * 16;
+}
+
+static dim3 node_grid(const Plan& p, const NodeGeom& g) {
+  const int tiles = (g.npos_total + 15) / 16;
+  return dim3((unsigned)((tiles + g.NT - 1) / g.NT), (unsigned)p.Nq);
+}
 
 template <typename T>
 static hipError_t node_fwd_t(const Plan& p, const NodeFwdLaunch& L, hipStream_t s) {
   NodeFwdArgs<T> a;
-  a.u = (const T*)L.u; a.Tt = (const T*)L.T; a.L1 = (const T*)L.L1; a.L2 = (const T*)L.L2; a.L3 = (const T*)L.L3;
+  a.u = (const T*)L.u; a.X = (const T*)L.X; a.Y = (const T*)L.Y;
+  a.L1 = (const T*)L.L1; a.L2 = (const T*)L.L2; a.L3 = (const T*)L.L3;
   a.mu_a = (const T*)L.mu_a; a.mu_s = (const T*)L.mu_s;
   a.u_out = (T*)L.u_out; a.L_out = (T*)L.L_out; a.flux = L.flux;
   a.Wt = p.dev.Wt; a.bc = p.dev.bc; a.kappa = p.dev.kappa;
@@ -443,20 +415,15 @@ static hipError_t node_fwd_t(const Plan& p, const NodeFwdLaunch& L, hipStream_t 
   a.geo = make_geom(p);
   a.step = L.step;
   a.cdt = p.prob.c * p.prob.dt;
-  const int TN = node_tile<T>(p);
-  const int Nn = (int)(p.nx * p.ny);
-  dim3 grid((unsigned)((Nn + TN - 1) / TN), (unsigned)p.Nq);
-  const size_t sh = sizeof(T) * (size_t)(2 * TN * (p.Mpad + 1) + 2 * TN);
-  const int qpt = (int)((p.G * TN + kNodeThreads - 1) / kNodeThreads);
-#define FWD_LAUNCH(TNV, Q) hipLaunchKernelGGL((node_fwd_kernel<T, TNV, Q>), grid, dim3(kNodeThreads), sh, s, a)
-  if (TN == 64) {
-    switch (qpt) { case 1: FWD_LAUNCH(64, 1); break; case 2: FWD_LAUNCH(64, 2); break;
-                   case 3: FWD_LAUNCH(64, 3); break; default: FWD_LAUNCH(64, 4); break; }
-  } else {
-    switch (qpt) { case 1: FWD_LAUNCH(32, 1); break; case 2: FWD_LAUNCH(32, 2); break;
-                   case 3: FWD_LAUNCH(32, 3); break; default: FWD_LAUNCH(32, 4); break; }
+  const dim3 grid = node_grid(p, a.geo), block((unsigned)(64 * a.geo.NT * a.geo.RT));
+  const size_t sh = node_shmem(a.geo, sizeof(T));
+  switch (a.geo.RT) {
+    case 1: hipLaunchKernelGGL((node_fwd_kernel<T, 1>), grid, block, sh, s, a); break;
+    case 2: hipLaunchKernelGGL((node_fwd_kernel<T, 2>), grid, block, sh, s, a); break;
+    case 3: hipLaunchKernelGGL((node_fwd_kernel<T, 3>), grid, block, sh, s, a); break;
+    case 4: hipLaunchKernelGGL((node_fwd_kernel<T, 4>), grid, block, sh, s, a); break;
+    default: hipLaunchKernelGGL((node_fwd_kernel<T, 0>), grid, block, sh, s, a); break;
   }
-#undef FWD_LAUNCH
   return hipGetLastError();
 }
 
@@ -467,28 +434,23 @@ hipError_t launch_node_fwd(const Plan& p, const NodeFwdLaunch& L, hipStream_t s)
 template <typename T>
 static hipError_t node_adj_t(const Plan& p, const NodeAdjLaunch& L, hipStream_t s) {
   NodeAdjArgs<T> a;
-  a.v1 = (T*)L.v1; a.v2 = (const T*)L.v2; a.v3 = (const T*)L.v3; a.v4 = (const T*)L.v4; a.u = (const T*)L.u;
+  a.atx = (const T*)L.atx; a.aty = (const T*)L.aty; a.ap1 = (T*)L.ap1; a.v1_out = (T*)L.v1_out;
+  a.v2 = (const T*)L.v2; a.v3 = (const T*)L.v3; a.v4 = (const T*)L.v4; a.u = (const T*)L.u;
   a.mu_a = (const T*)L.mu_a; a.mu_s = (const T*)L.mu_s; a.inj = L.inj;
-  a.w_out = (T*)L.w_out; a.p_out = (T*)L.p_out; a.ga = L.ga; a.gb = L.gb;
+  a.w_out = (T*)L.w_out; a.ga = L.ga; a.gb = L.gb;
   a.Wt = p.dev.Wt; a.bct = p.dev.bct; a.kappa = p.dev.kappa;
   a.geo = make_geom(p);
   a.step = L.step;
-  a.convert_v1 = L.convert_v1;
   a.cdt = p.prob.c * p.prob.dt;
-  const int TN = node_tile<T>(p);
-  const int Nn = (int)(p.nx * p.ny);
-  dim3 grid((unsigned)((Nn + TN - 1) / TN), (unsigned)p.Nq);
-  const size_t sh = sizeof(T) * (size_t)(3 * TN * (p.Mpad + 1) + 2 * TN + 2) + sizeof(double) * 2 * TN * p.G;
-  const int qpt = (int)((p.G * TN + kNodeThreads - 1) / kNodeThreads);
-#define ADJ_LAUNCH(TNV, Q) hipLaunchKernelGGL((node_adj_kernel<T, TNV, Q>), grid, dim3(kNodeThreads), sh, s, a)
-  if (TN == 64) {
-    switch (qpt) { case 1: ADJ_LAUNCH(64, 1); break; case 2: ADJ_LAUNCH(64, 2); break;
-                   case 3: ADJ_LAUNCH(64, 3); break; default: ADJ_LAUNCH(64, 4); break; }
-  } else {
-    switch (qpt) { case 1: ADJ_LAUNCH(32, 1); break; case 2: ADJ_LAUNCH(32, 2); break;
-                   case 3: ADJ_LAUNCH(32, 3); break; default: ADJ_LAUNCH(32, 4); break; }
+  const dim3 grid = node_grid(p, a.geo), block((unsigned)(64 * a.geo.NT * a.geo.RT));
+  const size_t sh = node_shmem(a.geo, sizeof(T));
+  switch (a.geo.RT) {
+    case 1: hipLaunchKernelGGL((node_adj_kernel<T, 1>), grid, block, sh, s, a); break;
+    case 2: hipLaunchKernelGGL((node_adj_kernel<T, 2>), grid, block, sh, s, a); break;
+    case 3: hipLaunchKernelGGL((node_adj_kernel<T, 3>), grid, block, sh, s, a); break;
+    case 4: hipLaunchKernelGGL((node_adj_kernel<T, 4>), grid, block, sh, s, a); break;
+    default: hipLaunchKernelGGL((node_adj_kernel<T, 0>), grid, block, sh, s, a); break;
   }
-#undef ADJ_LAUNCH
   return hipGetLastError();
 }
 
@@ -562,7 +524,7 @@ __global__ void grad_reduce_kernel(const double* __restrict__ ga, const double* 
 
 template <typename T>
 __global__ void unpermute_kernel(const T* __restrict__ st, T* __restrict__ out, const int32_t* __restrict__ slot_m,
-                                 int M, int G, int64_t Nn, int Nq) {
+                                 int M, int nx, int nxp, int64_t Nn, int Nq, int64_t grp_stride, int64_t inst_stride) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)Nq * Nn * M;
   if (t >= total) return;
@@ -570,7 +532,8 @@ __global__ void unpermute_kernel(const T* __restrict__ st, T* __restrict__ out, 
   const int64_t gn = (t / M) % Nn;
   const int q = (int)(t / (M * Nn));
   const int g = s / kGroup, r = s % kGroup;
-  const T v = st[(int64_t)q * G * Nn * kGroup + (int64_t)g * Nn * kGroup + gn * kGroup + r];
+  const int64_t j = gn / nx, i = gn - j * nx;
+  const T v = st[(int64_t)q * inst_stride + (int64_t)g * grp_stride + (j * nxp + i) * kGroup + r];
   out[((int64_t)q * Nn + gn) * M + slot_m[s]] = v;
 }
 
@@ -636,10 +599,10 @@ hipError_t launch_unpermute(const Plan& p, const void* state, void* out, hipStre
   const dim3 grid((unsigned)((total + 255) / 256));
   if (p.dtype == RTE_F64)
     hipLaunchKernelGGL(unpermute_kernel<double>, grid, dim3(256), 0, s, (const double*)state, (double*)out,
-                       p.dev.slot_m, (int)p.M, (int)p.G, Nn, (int)p.Nq);
+                       p.dev.slot_m, (int)p.M, (int)p.nx, (int)p.nxp, Nn, (int)p.Nq, p.grp_stride, p.inst_stride);
   else
     hipLaunchKernelGGL(unpermute_kernel<float>, grid, dim3(256), 0, s, (const float*)state, (float*)out,
-                       p.dev.slot_m, (int)p.M, (int)p.G, Nn, (int)p.Nq);
+                       p.dev.slot_m, (int)p.M, (int)p.nx, (int)p.nxp, Nn, (int)p.Nq, p.grp_stride, p.inst_stride);
   return hipGetLastError();
 }
 

@@ -159,7 +159,7 @@ static bool build_fc(const rte_problem& pb, int n, double h, std::vector<double>
     buf.push_back(std::cos(ang));
     buf.push_back(std::sin(ang));
   }
-  if (!fourstep_split(Np, &fc.n1, &fc.n2)) fc.n1 = fc.n2 = 0;
+  if (!fourstep_split(Np, &fc.n1, &fc.n2) || d * d + C * d > kFcTab) fc.n1 = fc.n2 = 0;
   return true;
 }
 
@@ -231,6 +231,12 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
   p.M = prob->M;
   p.G = p.M / kGroup;
   p.Mpad = ((p.M + 15) / 16) * 16;
+  {
+    const int64_t align = (prob->dtype == RTE_F64) ? 4 : 8;  // nodes per 128 bytes of one group
+    p.nxp = ((p.nx + align - 1) / align) * align;
+  }
+  p.grp_stride = p.ny * p.nxp * kGroup;
+  p.inst_stride = p.G * p.grp_stride;
   p.K = prob->K;
   p.Nd = n_det;
   p.nbeams = n_beams;
@@ -411,6 +417,9 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
     return RTE_EUNSUPPORTED;
   }
 
+  p.fc_same = p.fcx.n == p.fcy.n && p.fcx.Np == p.fcy.Np && p.fcx.E == p.fcy.E &&
+              std::equal(fcbuf.begin() + ox[1], fcbuf.begin() + ox[2], fcbuf.begin() + oy[1]);
+
   // ---- upload
   std::vector<int32_t> slotm(p.slot_m.begin(), p.slot_m.end());
   bool ok = upload(xi, &p.dev.xi) && upload(eta, &p.dev.eta) && upload(Wt, &p.dev.Wt) && upload(bc, &p.dev.bc) &&
@@ -471,14 +480,19 @@ hipError_t prof_begin(Plan& p, int cls, hipStream_t s, hipEvent_t* stop) {
 hipError_t prof_end(hipEvent_t stop, hipStream_t s) { return stop ? hipEventRecord(stop, s) : hipSuccess; }
 
 // ---------------------------------------------------------------- workspace
-int64_t state_elems(const Plan& p) { return p.Nq * p.M * p.nx * p.ny; }
+int64_t state_elems(const Plan& p) { return p.Nq * p.inst_stride; }
 
 static int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
 struct Layout {
-  int64_t states, ckpts, work_u, lring, tx, tt, vring, wbuf, flux, ga, gb, gbar, scratch, total;
+  int64_t states, ckpts, work_u, lring, tx, ty, vring, atx, aty, ap1, flux, ga, gb, gbar, scratch, total;
 };
 
+// Forward: lring[3], tx, ty.  Adjoint: vring[4], w (aliases tx), the carries
+// atx, aty, ap1.  With every state kept no forward step runs during the
+// adjoint, so vring[0..2] alias the L ring and atx aliases ty; with
+// checkpoints the segment replays need the forward arrays while the adjoint
+// ring and carries are live, so those are separate.
 static Layout layout(const Plan& p, bool adj) {
   const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
   const int64_t S = align256(state_elems(p) * es);
@@ -496,11 +510,15 @@ static Layout layout(const Plan& p, bool adj) {
   o += 3 * S;
   L.tx = o;
   o += S;
-  L.tt = o;
+  L.ty = o;
   o += S;
   L.vring = o;
-  if (adj) o += ck ? 4 * S : S;  // store-all mode reuses the L ring for 3 of the 4 slots
-  L.wbuf = o;
+  if (adj) o += ck ? 4 * S : S;
+  L.atx = o;
+  if (adj && ck) o += S;
+  L.aty = o;
+  if (adj) o += S;
+  L.ap1 = o;
   if (adj) o += S;
   L.flux = o;
   o += align256(p.Nq * (p.K + 1) * 4 * p.npos * 8);
@@ -534,15 +552,20 @@ bool map_workspace(const Plan& p, void* base, int64_t bytes, bool adj, Workspace
   }
   for (int k = 0; k < 3; ++k) ws->lring[k] = b + L.lring + k * S;
   ws->tx = b + L.tx;
-  ws->tt = b + L.tt;
+  ws->ty = b + L.ty;
   if (adj) {
-    if (p.ckpt_every > 0) {
+    const bool ck = p.ckpt_every > 0;
+    if (ck) {
       for (int k = 0; k < 4; ++k) ws->vring[k] = b + L.vring + k * S;
+      ws->atx = b + L.atx;
     } else {
       for (int k = 0; k < 3; ++k) ws->vring[k] = ws->lring[k];
       ws->vring[3] = b + L.vring;
+      ws->atx = ws->ty;
     }
-    ws->wbuf = b + L.wbuf;
+    ws->wbuf = ws->tx;
+    ws->aty = b + L.aty;
+    ws->ap1 = b + L.ap1;
     ws->ga = reinterpret_cast<double*>(b + L.ga);
     ws->gb = reinterpret_cast<double*>(b + L.gb);
     ws->gbar = reinterpret_cast<double*>(b + L.gbar);

@@ -14,9 +14,8 @@ namespace rte {
 constexpr int kGroup = 4;        // ordinate slots per storage group (one reflection orbit)
 constexpr int kMaxPasses = 12;   // FFT passes (radices 2,3,4,5)
 constexpr int kMaxFcD = 8;       // matching points supported
-constexpr int kNodeTile = 64;    // nodes per node-pass workgroup
-constexpr int kNodeThreads = 256;
-constexpr int kLineThreads = 128;
+constexpr int kLineThreads = 128; // generic (Stockham) line kernel
+constexpr int kFcTab = 256;      // Q (d*d) and A (C*d) entries staged by the four-step kernel
 
 void set_error(const std::string& msg);
 const char* last_error();
@@ -82,6 +81,12 @@ struct Plan {
   rte_problem prob{};
   int dtype = RTE_F64;
   int64_t nx = 0, ny = 0, M = 0, G = 0, Mpad = 0, K = 0, Nq = 0, Nd = 0, nbeams = 0;
+  // state layout [q][g][j][i][r]: rows padded to nxp nodes so that every row
+  // starts on a 128-byte boundary (4 FP64 or 8 FP32 nodes of one group)
+  int64_t nxp = 0;
+  int64_t grp_stride = 0;   // ny * nxp * kGroup elements
+  int64_t inst_stride = 0;  // G * grp_stride
+  bool fc_same = false;     // x and y FC plans identical: both line sets in one launch
   int64_t nb = 0;     // boundary nodes 2(nx+ny)-4
   int64_t npos = 0;   // max(nx, ny)
   std::vector<int> slot_m;  // slot -> ordinate index
@@ -115,10 +120,14 @@ struct Workspace {
   void* ckpts = nullptr;     // checkpoint mode: n_ckpt * 4 states (u, L1, L2, L3)
   void* work_u[2] = {nullptr, nullptr};  // checkpoint mode: ping-pong current state
   void* lring[3] = {nullptr, nullptr, nullptr};
-  void* tx = nullptr;        // line-pass intermediate
-  void* tt = nullptr;        // second intermediate (T, or adjoint P1)
-  void* vring[4] = {nullptr, nullptr, nullptr, nullptr};  // adjoint ring
-  void* wbuf = nullptr;      // adjoint w
+  void* tx = nullptr;        // forward: -xi Dx u^n
+  void* ty = nullptr;        // forward: -eta Dy u^n
+  void* vring[4] = {nullptr, nullptr, nullptr, nullptr};  // adjoint ring v^k
+  void* wbuf = nullptr;      // adjoint w^n (aliases tx: live only inside one adjoint step)
+  // adjoint carries from step n+1 to step n: ubar^{n+1} = ap1 - c dt (atx + aty)
+  void* atx = nullptr;       // Dx^T(xi w^{n+1})
+  void* aty = nullptr;       // Dy^T(eta w^{n+1})
+  void* ap1 = nullptr;       // v^{n+2} + c dt (b W w - (a+b) w)^{n+1} + D_e^T Gbar
   double* flux = nullptr;    // [Nq][K+1][4][npos] detector flux / adjoint injection
   double* ga = nullptr;      // [Nq][ny*nx]
   double* gb = nullptr;
@@ -132,28 +141,30 @@ bool map_workspace(const Plan& p, void* base, int64_t bytes, bool with_adjoint, 
 
 // ---------------------------------------------------------------- kernel launchers
 enum LineMode {
-  LINE_FWD_X = 0,  // out = -xi * Dx(in)
-  LINE_FWD_Y = 1,  // out = aux - eta * Dy(in)
-  LINE_ADJ_X = 2,  // out = Dx^T(xi * in)
-  LINE_ADJ_Y = 3   // out = aux2 - cdt * (aux + Dy^T(eta * in))
+  LINE_FWD = 0,  // out_x = -xi Dx(in), out_y = -eta Dy(in)
+  LINE_ADJ = 1   // out_x = Dx^T(xi in), out_y = Dy^T(eta in)
 };
 
+// Both line sets of one state (dirs bit 0: x lines / rows, bit 1: y lines /
+// columns).  Launched as one kernel when the two FC plans coincide.
 struct LineLaunch {
   const void* in;
-  const void* aux;
-  const void* aux2;
-  void* out;
+  void* out_x;
+  void* out_y;
   int mode;
-  int dir;          // 0: x lines (rows), 1: y lines (columns)
-  double cdt;
+  int dirs;
 };
 
-hipError_t launch_line(const Plan& p, const LineLaunch& L, hipStream_t s);
-hipError_t launch_line4(const Plan& p, const LineLaunch& L, hipStream_t s);
+hipError_t launch_lines(const Plan& p, const LineLaunch& L, hipStream_t s);
+// four-step kernel for one direction set; hipErrorNotSupported if Np has no split
+hipError_t launch_lines4(const Plan& p, const LineLaunch& L, hipStream_t s);
+// generic Stockham kernel for one direction
+hipError_t launch_line_generic(const Plan& p, const void* in, void* out, int mode, int dir, hipStream_t s);
 
 struct NodeFwdLaunch {
   const void* u;       // u^n
-  const void* T;       // advection term from the line passes
+  const void* X;       // -xi Dx u^n
+  const void* Y;       // -eta Dy u^n
   const void* L1;      // L^{n-1}
   const void* L2;
   const void* L3;
@@ -167,7 +178,10 @@ struct NodeFwdLaunch {
 hipError_t launch_node_fwd(const Plan& p, const NodeFwdLaunch& L, hipStream_t s);
 
 struct NodeAdjLaunch {
-  void* v1;            // ring slot n+1 (holds ubar^{n+1}; converted in place to v^{n+1})
+  const void* atx;     // pieces of ubar^{n+1}: ap1 - c dt (atx + aty)
+  const void* aty;
+  void* ap1;           // read as P1^{n+1}, overwritten with P1^n
+  void* v1_out;        // ring slot for v^{n+1} = P^T ubar^{n+1}
   const void* v2;      // v^{n+2}
   const void* v3;
   const void* v4;
@@ -176,11 +190,9 @@ struct NodeAdjLaunch {
   const void* mu_s;
   const double* inj;   // [Nq][K+1][4][npos] detector injection
   void* w_out;         // w^n
-  void* p_out;         // P1
-  double* ga;
+  double* ga;          // [Nq][ny*nx]
   double* gb;
   int step;            // n
-  int convert_v1;      // apply P^T to the boundary nodes of v1 (0 when slot n+1 is beyond K)
 };
 hipError_t launch_node_adj(const Plan& p, const NodeAdjLaunch& L, hipStream_t s);
 

@@ -283,7 +283,7 @@ class Batch:
         return J, da, db, G
 
 
-KERNEL_CLASSES = ("line_x_fwd", "line_y_fwd", "node_fwd", "node_adj", "line_x_adj", "line_y_adj")
+KERNEL_CLASSES = ("lines_fwd", "node_fwd", "node_adj", "lines_adj")
 
 
 def profile_enable(plan, on=True):
