@@ -151,6 +151,8 @@ def main():
     a_bg = torch.full((ny, nx), 0.2, device="cuda", dtype=tdt)
     b_bg = torch.full((ny, nx), 50.0, device="cuda", dtype=tdt)
     log("bench: %s, workspace %.1f GB" % (spec.name, plan.workspace_bytes(True) / 1e9))
+    sched = plan.autotune(a_bg, b_bg, cache=False)
+    log("bench: autotuned schedule %s" % sched)
     G_true = plan.forward(a_true, b_true)
     noise = torch.tensor(W.measured_noise(1, tuple(G_true.shape)), device="cuda")
     Gm = (G_true * noise).contiguous()
@@ -227,6 +229,7 @@ def main():
         "config": {"workload": spec.name, "grid": "%dx%d" % (nx, ny), "ordinates": spec.M, "time_steps": spec.K,
                    "sources": spec.Nq, "detectors": len(spec.detectors), "states": "all kept (no replay)",
                    "path": "plain (one source: batched == plain)", "launch": "one HIP graph per gradient",
+                   "schedule": {k: v for k, v in sched.items() if k != "cached"},
                    "eager_ms_per_step": round(1000 * eager_s, 2)},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic["bytes"],

@@ -165,6 +165,44 @@ int rte_batch_gradient(rte_batch* batch, const void* const* mu_a, const void* co
                        double* const* dmu_s, double* const* G, void* const* workspaces,
                        const int64_t* workspace_bytes, void* stream);
 
+/* Launch schedule of the per-step kernels.  The units-per-wave and
+ * tiles-per-block choices compute the same result bit for bit; the generic
+ * line kernel computes the same operator with another FFT factorisation
+ * (equal to rounding).  Zero fields mean the default.  The waves-per-unit
+ * choice is bitwise neutral as well.
+ *   line_units_per_wave : 1 or 2 work units (two lines x four slots of one
+ *                         ordinate group) per workgroup of the four-step line
+ *                         kernel, transformed one after the other
+ *   line_waves_per_unit : 1 or 2 waves sharing the transforms of one unit
+ *   line_generic        : 1 = use the generic Stockham line kernel even where
+ *                         the extended length has a four-step split
+ *   node_tiles_per_block: 16-node tiles per workgroup of the node passes
+ *                         (1, 2 or 4; times the 16-slot row tiles, at most 8
+ *                         waves; plans with M > 64 always use 1)          */
+typedef struct {
+  int32_t line_units_per_wave;
+  int32_t line_generic;
+  int32_t node_tiles_per_block;
+  int32_t line_waves_per_unit;
+} rte_schedule;
+
+/* Current schedule of the plan (defaults resolved). */
+int rte_plan_get_schedule(const rte_plan* plan, rte_schedule* out);
+
+/* Sets the schedule; RTE_EINVAL for values outside the ranges above.  A
+ * recorded graph is dropped (the next graph-mode call re-records).      */
+int rte_plan_set_schedule(rte_plan* plan, const rte_schedule* sched);
+
+/* Autotuner: times every admissible schedule of the four per-step kernel
+ * classes on this plan's shapes (a few launches each, on `stream`, with
+ * HIP events; the call synchronizes the stream), keeps the fastest choice
+ * per class and stores it in the plan; `chosen` (host, may be NULL)
+ * receives it.  Uses the gradient workspace (>= rte_workspace_bytes(plan,
+ * 1)) as scratch: any saved forward is invalidated.  mu_a, mu_s as in
+ * rte_forward.  Not for use under stream capture.                         */
+int rte_plan_autotune(rte_plan* plan, const void* mu_a, const void* mu_s, void* workspace,
+                      int64_t workspace_bytes, void* stream, rte_schedule* chosen);
+
 /* Instrumentation.  Kernel classes of one time step: */
 typedef enum {
   RTE_K_LINES_FWD = 0, /* FC derivatives along x and y lines          */

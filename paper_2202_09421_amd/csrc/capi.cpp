@@ -211,7 +211,7 @@ int enqueue_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
 // Graph mode: record the whole sequence once per argument set, then replay.
 int graph_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
   const void* key[9] = {a.mu_a, a.mu_s, a.G_meas, a.J, a.dmu_a, a.dmu_s, a.G, a.ws, nullptr};
-  bool same = p.gexec != nullptr && p.gkey_bytes == a.wsb;
+  bool same = p.gexec != nullptr && p.gkey_bytes == a.wsb && p.gkey_sched == p.sched_version;
   for (int k = 0; k < 8 && same; ++k) same = (p.gkey[k] == key[k]);
   if (!same) {
     if (p.gexec) {
@@ -236,9 +236,125 @@ int graph_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
     RTE_CHECK(ei);
     for (int k = 0; k < 8; ++k) p.gkey[k] = key[k];
     p.gkey_bytes = a.wsb;
+    p.gkey_sched = p.sched_version;
   }
   RTE_CHECK(hipGraphLaunch(p.gexec, st));
   p.have_forward = true;
+  return RTE_OK;
+}
+
+// ---- autotuner
+bool sched_ok(const Plan& p, const rte_schedule& s) {
+  return (s.line_units_per_wave == 1 || s.line_units_per_wave == 2) && (s.line_generic == 0 || s.line_generic == 1) &&
+         node_tiles_ok(p, s.node_tiles_per_block) && (s.line_waves_per_unit == 1 || s.line_waves_per_unit == 2);
+}
+
+// Mean milliseconds per call of `launch` over `reps` calls after one warm-up.
+template <typename F>
+int time_launches(hipStream_t st, int reps, F&& launch, float* ms) {
+  hipEvent_t e0, e1;
+  RTE_CHECK(hipEventCreate(&e0));
+  RTE_CHECK(hipEventCreate(&e1));
+  hipError_t err = launch();
+  if (err == hipSuccess) err = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
+  if (err == hipSuccess) err = hipEventRecord(e1, st);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float t = 0.0f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  RTE_CHECK(err);
+  *ms = t / reps;
+  return RTE_OK;
+}
+
+int autotune(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t wsb, hipStream_t st, rte_schedule* out) {
+  Workspace ws;
+  if (!map_workspace(p, wsp, wsb, true, &ws)) {
+    std::ostringstream o;
+    o << "workspace too small: need " << workspace_bytes(p, true) << " bytes";
+    set_error(o.str());
+    return RTE_ENOMEM;
+  }
+  p.have_forward = false;
+  const bool prof = p.prof;
+  p.prof = false;
+  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
+  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  void* u0 = ws.states;
+  void* u1 = static_cast<char*>(ws.states) + S;
+  void* arrays[] = {u0, u1, ws.lring[0], ws.lring[1], ws.lring[2], ws.tx, ws.ty, ws.vring[0], ws.vring[1],
+                    ws.vring[2], ws.vring[3], ws.atx, ws.aty, ws.ap1};
+  for (void* a : arrays) RTE_CHECK(launch_zero(a, S, st));
+  RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
+  RTE_CHECK(launch_zero(ws.ga, p.Nq * p.nx * p.ny * 8, st));
+  RTE_CHECK(launch_zero(ws.gb, p.Nq * p.nx * p.ny * 8, st));
+  const int reps = 5;
+  const rte_schedule start = p.sched;
+  rte_schedule best = p.sched;
+
+  // line passes: forward and transpose launches of each admissible variant
+  struct LineCand {
+    int upw, nw, generic;
+  };
+  std::vector<LineCand> line_cands;
+  const bool four = p.fcx.n1 > 0 || p.fcy.n1 > 0;
+  if (four)
+    for (int upw : {2, 1})
+      for (int nw : {1, 2}) line_cands.push_back({upw, nw, 0});
+  line_cands.push_back({1, 1, 1});
+  float best_ms = 1e30f;
+  for (const auto& c : line_cands) {
+    p.sched.line_units_per_wave = c.upw;
+    p.sched.line_waves_per_unit = c.nw;
+    p.sched.line_generic = c.generic;
+    float f = 0.0f, b = 0.0f;
+    const LineLaunch lf{u0, ws.tx, ws.ty, LINE_FWD, 3};
+    const LineLaunch lb{ws.wbuf, ws.atx, ws.aty, LINE_ADJ, 3};
+    int rc = time_launches(st, reps, [&] { return launch_lines(p, lf, st); }, &f);
+    if (rc == RTE_OK) rc = time_launches(st, reps, [&] { return launch_lines(p, lb, st); }, &b);
+    if (rc != RTE_OK) {
+      p.sched = start;
+      p.prof = prof;
+      return rc;
+    }
+    if (f + b < best_ms) {
+      best_ms = f + b;
+      best.line_units_per_wave = c.upw;
+      best.line_waves_per_unit = c.nw;
+      best.line_generic = c.generic;
+    }
+  }
+  p.sched.line_units_per_wave = best.line_units_per_wave;
+  p.sched.line_waves_per_unit = best.line_waves_per_unit;
+  p.sched.line_generic = best.line_generic;
+
+  // node passes: tiles per block
+  best_ms = 1e30f;
+  for (int nt : {1, 2, 4}) {
+    if (!node_tiles_ok(p, nt)) continue;
+    p.sched.node_tiles_per_block = nt;
+    NodeFwdLaunch nf{u0, ws.tx, ws.ty, ws.lring[1], ws.lring[2], ws.lring[0], mu_a, mu_s, u1, ws.lring[0], ws.flux, 0};
+    NodeAdjLaunch na{ws.atx, ws.aty, ws.ap1, ws.vring[1], ws.vring[2], ws.vring[3], ws.vring[0], u0,
+                     mu_a, mu_s, ws.flux, ws.wbuf, ws.ga, ws.gb, (int)p.K};
+    float f = 0.0f, b = 0.0f;
+    int rc = time_launches(st, reps, [&] { return launch_node_fwd(p, nf, st); }, &f);
+    if (rc == RTE_OK) rc = time_launches(st, reps, [&] { return launch_node_adj(p, na, st); }, &b);
+    if (rc != RTE_OK) {
+      p.sched = start;
+      p.prof = prof;
+      return rc;
+    }
+    if (f + b < best_ms) {
+      best_ms = f + b;
+      best.node_tiles_per_block = nt;
+    }
+  }
+  p.sched = best;
+  ++p.sched_version;
+  p.prof = prof;
+  if (out) *out = best;
   return RTE_OK;
 }
 
@@ -351,6 +467,46 @@ int rte_plan_set_graph(rte_plan* h, int enable) {
   return RTE_OK;
 }
 
+int rte_plan_get_schedule(const rte_plan* h, rte_schedule* out) {
+  if (!nonnull(h, "plan") || !nonnull(out, "out")) return RTE_EINVAL;
+  *out = reinterpret_cast<const Plan*>(h)->sched;
+  return RTE_OK;
+}
+
+int rte_plan_set_schedule(rte_plan* h, const rte_schedule* sched) {
+  if (!nonnull(h, "plan") || !nonnull(sched, "sched")) return RTE_EINVAL;
+  Plan& p = *reinterpret_cast<Plan*>(h);
+  rte_schedule s = *sched;
+  if (s.line_units_per_wave == 0) s.line_units_per_wave = 2;
+  if (s.line_waves_per_unit == 0) s.line_waves_per_unit = 1;
+  if (s.node_tiles_per_block == 0) s.node_tiles_per_block = node_tiles_default(p);
+  if (!sched_ok(p, s)) {
+    std::ostringstream o;
+    o << "schedule out of range: line_units_per_wave " << s.line_units_per_wave << ", line_waves_per_unit "
+      << s.line_waves_per_unit << ", line_generic " << s.line_generic << ", node_tiles_per_block "
+      << s.node_tiles_per_block << " (M = " << p.M << ")";
+    set_error(o.str());
+    return RTE_EINVAL;
+  }
+  p.sched = s;
+  ++p.sched_version;
+  return RTE_OK;
+}
+
+int rte_plan_autotune(rte_plan* h, const void* mu_a, const void* mu_s, void* workspace, int64_t workspace_bytes,
+                      void* stream, rte_schedule* chosen) {
+  if (!nonnull(h, "plan") || !nonnull(mu_a, "mu_a") || !nonnull(mu_s, "mu_s") || !nonnull(workspace, "workspace"))
+    return RTE_EINVAL;
+  try {
+    set_error("");
+    return autotune(*reinterpret_cast<Plan*>(h), mu_a, mu_s, workspace, workspace_bytes,
+                    static_cast<hipStream_t>(stream), chosen);
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RTE_EINVAL;
+  }
+}
+
 int rte_batch_create(rte_plan* const* plans, int64_t n, rte_batch** out) {
   if (!nonnull(plans, "plans") || !nonnull(out, "out")) return RTE_EINVAL;
   *out = nullptr;
@@ -402,9 +558,10 @@ int rte_batch_gradient(rte_batch* h, const void* const* mu_a, const void* const*
         set_error("a pointer of batch entry " + std::to_string(i) + " is NULL");
         return RTE_EINVAL;
       }
-      const void* k[9] = {args[i].mu_a, args[i].mu_s, args[i].G_meas, args[i].J, args[i].dmu_a, args[i].dmu_s,
-                          args[i].G, args[i].ws, reinterpret_cast<const void*>(args[i].wsb)};
-      key.insert(key.end(), k, k + 9);
+      const void* k[10] = {args[i].mu_a, args[i].mu_s, args[i].G_meas, args[i].J, args[i].dmu_a, args[i].dmu_s,
+                           args[i].G, args[i].ws, reinterpret_cast<const void*>(args[i].wsb),
+                           reinterpret_cast<const void*>(b.plans[i]->sched_version)};
+      key.insert(key.end(), k, k + 10);
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (!b.gexec || key != b.key) {

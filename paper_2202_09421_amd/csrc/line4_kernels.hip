@@ -40,11 +40,11 @@ struct Lines4Args {
   int nunits;
 };
 
-constexpr int kLP = 4;  // complex lines per unit
+constexpr int kLP = 4;  // complex lines per unit (two lines x slot pairs)
 constexpr size_t kLines4MaxLds = 64 * 1024;
 
-// lane-owned loads of one unit: point i of line it (0/1) for e = lane + 64 t,
-// i = e / 2, it = e % 2; 4 slots each
+// thread-owned loads of one unit: point i of line it (0/1) for
+// e = tid + NTH t, i = e / 2, it = e % 2; 4 slots each
 template <typename T, int TMAX>
 struct UnitRegs {
   T v[TMAX][4];
@@ -78,14 +78,14 @@ __device__ __forceinline__ UnitDesc decode_unit(const Lines4Args<T>& a, int u) {
   return d;
 }
 
-template <typename T, int TMAX>
-__device__ __forceinline__ void load_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int lane,
+template <typename T, int TMAX, int NTH>
+__device__ __forceinline__ void load_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int tid,
                                           UnitRegs<T, TMAX>& R) {
   const T* in = a.in + d.base;
   const int64_t ls = a.line_stride[d.dir], ps = a.pt_stride[d.dir];
 #pragma unroll
   for (int t = 0; t < TMAX; ++t) {
-    const int e = lane + 64 * t, it = e & 1, i = e >> 1;
+    const int e = tid + NTH * t, it = e & 1, i = e >> 1;
     if (d.live && i < n && (it == 0 || d.has1)) {
       const T* p = in + it * ls + (int64_t)i * ps;
       if constexpr (sizeof(T) == 8) {
@@ -103,106 +103,105 @@ __device__ __forceinline__ void load_unit(const Lines4Args<T>& a, const UnitDesc
   }
 }
 
-// LDS layout (doubles): buf [kLP][N1][N2+1] complex | cs [2][kLP][2][kMaxFcD]
-// complex | roots [N] complex | mu [N] | Q, A [kFcTab]
+// LDS layout (doubles): buf [kLP][LSZ] complex (rows of N2 + 1 entries, line
+// stride LSZ = 2 mod 4 entries so that the two lines stored by neighbouring
+// lanes fall in different bank halves) | fold [kLP][2 kMaxFcD] complex |
+// roots, complex, entry e at e + e / 16 (spreads the strided twiddle reads
+// over the banks) | mu [N] | continuation matrix [(C+E) x 2d]
 template <int N1, int N2>
 struct L4Smem {
   static constexpr int N = N1 * N2;
   static constexpr int PS = N2 + 1;
-  static constexpr int LSZ = N1 * PS;
+  static constexpr int LSZ0 = N1 * PS;
+  static constexpr int LSZ = LSZ0 + (6 - LSZ0 % 4) % 4;
+  static constexpr int NR = N + N / 16 + 1;
   static constexpr int BUF = 2 * kLP * LSZ;
-  static constexpr int CS = 2 * 2 * kLP * 2 * kMaxFcD;
-  static constexpr int ROOTS = 2 * N;
+  static constexpr int FOLD = 2 * kLP * 2 * kMaxFcD;
+  static constexpr int ROOTS = 2 * NR;
   static constexpr int MU = N;
-  static constexpr int TOTAL = BUF + CS + ROOTS + MU + kFcTab;
-  static constexpr size_t bytes = sizeof(double) * (size_t)TOTAL;
+  static constexpr int FIXED = BUF + FOLD + ROOTS + MU;
+  // nmx = (C + E) * 2d continuation entries
+  static constexpr size_t bytes(int nmx) { return sizeof(double) * (size_t)(FIXED + nmx); }
 };
 
-template <typename T, int TMAX, int N1, int N2>
+__device__ __forceinline__ int rix(int e) { return e + (e >> 4); }
+
+template <typename T, int TMAX, int N1, int N2, int NTH>
 __device__ __forceinline__ void stage_unit(const UnitRegs<T, TMAX>& R, const UnitDesc& d, const double* coef,
-                                           bool adj, int n, int lane, cx<double>* buf) {
-  constexpr int N = N1 * N2, PS = N2 + 1, LSZ = N1 * PS;
+                                           bool adj, int n, int tid, cx<double>* buf) {
+  typedef L4Smem<N1, N2> SM;
   double cf[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) cf[r] = adj ? coef[d.s0 + r] : 1.0;
 #pragma unroll
   for (int t = 0; t < TMAX; ++t) {
-    const int e = lane + 64 * t, it = e & 1, i = e >> 1;
+    const int e = tid + NTH * t, it = e & 1, i = e >> 1;
     if (i < n) {
-      const int ph = (i / N2) * PS + i % N2;
-      buf[(2 * it) * LSZ + ph] = {cf[0] * (double)R.v[t][0], cf[1] * (double)R.v[t][1]};
-      buf[(2 * it + 1) * LSZ + ph] = {cf[2] * (double)R.v[t][2], cf[3] * (double)R.v[t][3]};
+      const int ph = (i / N2) * SM::PS + i % N2;
+      buf[(2 * it) * SM::LSZ + ph] = {cf[0] * (double)R.v[t][0], cf[1] * (double)R.v[t][1]};
+      buf[(2 * it + 1) * SM::LSZ + ph] = {cf[2] * (double)R.v[t][2], cf[3] * (double)R.v[t][3]};
     }
   }
   if (adj) {
-    const int ext = N - n;
-    for (int e = lane; e < kLP * ext; e += 64) {
+    const int ext = SM::N - n;
+    for (int e = tid; e < kLP * ext; e += NTH) {
       const int l = e / ext, i = n + e % ext;
-      buf[l * LSZ + (i / N2) * PS + i % N2] = {0.0, 0.0};
+      buf[l * SM::LSZ + (i / N2) * SM::PS + i % N2] = {0.0, 0.0};
     }
   }
 }
 
+// Store one complex point of complex line l (line l / 2 of the pair, slots
+// 2 (l % 2) and 2 (l % 2) + 1), scaled by (c0, c1).
+template <typename T>
+__device__ __forceinline__ void store_pt(T* out, int64_t ls, int64_t ps, int l, int p, double re, double im, double c0,
+                                         double c1) {
+  T* q = out + (l >> 1) * ls + (int64_t)p * ps + 2 * (l & 1);
+  if constexpr (sizeof(T) == 8) {
+    *reinterpret_cast<double2*>(q) = make_double2(c0 * re, c1 * im);
+  } else {
+    *reinterpret_cast<float2*>(q) = make_float2(float(c0 * re), float(c1 * im));
+  }
+}
+
 // Continuation, derivative (or its transpose) and store of one staged unit.
-template <typename T, bool ADJ, int TMAX, int N1, int N2>
-__device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int dd, int C, int E,
-                                               int lane, cx<double>* buf, cx<double>* cs, const double* roots,
-                                               const double* mu, const double* Qs, const double* As) {
-  constexpr int N = N1 * N2, PS = N2 + 1, LSZ = N1 * PS;
+template <typename T, bool ADJ, int N1, int N2, int NTH>
+__device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int dd, int CE,
+                                               int tid, cx<double>* buf, cx<double>* fold, const cx<double>* roots,
+                                               const double* mu, const double* Mx) {
+  typedef L4Smem<N1, N2> SM;
+  constexpr int N = SM::N, PS = SM::PS, LSZ = SM::LSZ;
   auto ph = [](int i) { return (i / N2) * PS + i % N2; };
 
   if (!ADJ) {
-    // Gram projections of the matching values (Sec. 4.3 step 1)
-    for (int t = lane; t < kLP * 2 * dd; t += 64) {
-      const int l = t / (2 * dd), rem = t % (2 * dd), end = rem / dd, j = rem % dd;
-      double sr = 0, si = 0;
+    // extension values (Sec. 4.3 steps 1-4 as one linear map of the 2d
+    // matching values); lane p < C + E computes position n + p of each line
+    if (tid < CE) {
+      const int lane = tid;
+      double sr[kLP], si[kLP];
+#pragma unroll
+      for (int l = 0; l < kLP; ++l) sr[l] = si[l] = 0.0;
 #pragma unroll
       for (int k = 0; k < kMaxFcD; ++k) {
         if (k < dd) {
-          const double qv = Qs[k * dd + j];
-          const cx<double> v = buf[l * LSZ + ph(end ? n - dd + k : dd - 1 - k)];
-          sr += qv * v.re;
-          si += qv * v.im;
-        }
-      }
-      cs[(l * 2 + end) * kMaxFcD + j] = {sr, si};
-    }
-    __syncthreads();
-    // blends to zero, E zeros, sum (steps 2-4)
-    const int CE = C + E;
-    for (int t = lane; t < kLP * CE; t += 64) {
-      const int l = t / CE, p = t % CE;
-      double sr = 0, si = 0;
-      if (p < C) {
+          const double mr = Mx[lane * 2 * dd + k], ml = Mx[lane * 2 * dd + dd + k];
 #pragma unroll
-        for (int j = 0; j < kMaxFcD; ++j) {
-          if (j < dd) {
-            const double av = As[p * dd + j];
-            const cx<double> c = cs[(l * 2 + 1) * kMaxFcD + j];
-            sr += av * c.re;
-            si += av * c.im;
+          for (int l = 0; l < kLP; ++l) {
+            const cx<double> gr = buf[l * LSZ + ph(n - dd + k)];
+            const cx<double> gl = buf[l * LSZ + ph(dd - 1 - k)];
+            sr[l] += mr * gr.re + ml * gl.re;
+            si[l] += mr * gr.im + ml * gl.im;
           }
         }
       }
-      if (p >= E) {
-        const int pp = CE - 1 - p;
 #pragma unroll
-        for (int j = 0; j < kMaxFcD; ++j) {
-          if (j < dd) {
-            const double av = As[pp * dd + j];
-            const cx<double> c = cs[(l * 2 + 0) * kMaxFcD + j];
-            sr += av * c.re;
-            si += av * c.im;
-          }
-        }
-      }
-      buf[l * LSZ + ph(n + p)] = {sr, si};
+      for (int l = 0; l < kLP; ++l) buf[l * LSZ + ph(n + lane)] = {sr[l], si[l]};
     }
     __syncthreads();
   }
 
   // step A: length-N1 transforms along the stride-N2 index
-  for (int job = lane; job < kLP * N2; job += 64) {
+  for (int job = tid; job < kLP * N2; job += NTH) {
     const int l = job / N2, n2 = job % N2;
     cx<double> x[N1];
 #pragma unroll
@@ -210,15 +209,15 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
     Dft<N1, -1, double>::run(x);
 #pragma unroll
     for (int k1 = 1; k1 < N1; ++k1) {
-      const int e = (n2 * k1) % N;
-      x[k1] = cx_rot(x[k1], roots[2 * e], roots[2 * e + 1]);
+      const cx<double> w = roots[rix((n2 * k1) % N)];
+      x[k1] = cx_rot(x[k1], w.re, w.im);
     }
 #pragma unroll
     for (int i = 0; i < N1; ++i) buf[l * LSZ + i * PS + n2] = x[i];
   }
   __syncthreads();
   // step B: length-N2 transforms, derivative factor, inverse transforms
-  for (int job = lane; job < kLP * N1; job += 64) {
+  for (int job = tid; job < kLP * N1; job += NTH) {
     const int l = job / N1, k1 = job % N1;
     cx<double> x[N2];
 #pragma unroll
@@ -233,15 +232,16 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
     Dft<N2, 1, double>::run(x);
 #pragma unroll
     for (int n2 = 1; n2 < N2; ++n2) {
-      const int e = (n2 * k1) % N;
-      x[n2] = cx_rot(x[n2], roots[2 * e], -roots[2 * e + 1]);
+      const cx<double> w = roots[rix((n2 * k1) % N)];
+      x[n2] = cx_rot(x[n2], w.re, -w.im);
     }
 #pragma unroll
     for (int i = 0; i < N2; ++i) buf[l * LSZ + k1 * PS + i] = x[i];
   }
   __syncthreads();
+
   // step A': inverse length-N1 transforms
-  for (int job = lane; job < kLP * N2; job += 64) {
+  for (int job = tid; job < kLP * N2; job += NTH) {
     const int l = job / N2, n2 = job % N2;
     cx<double> x[N1];
 #pragma unroll
@@ -252,35 +252,20 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
   }
   __syncthreads();
 
-  cx<double>* gs = cs + kLP * 2 * kMaxFcD;
   if (ADJ) {
-    // fold the extension region back onto the first and last d points
-    for (int t = lane; t < kLP * 2 * dd; t += 64) {
-      const int l = t / (2 * dd), rem = t % (2 * dd), end = rem / dd, j = rem % dd;
-      double sr = 0, si = 0;
-#pragma unroll 5
-      for (int p = 0; p < C; ++p) {
-        const double av = As[p * dd + j];
-        const cx<double> v = buf[l * LSZ + ph(end ? n + p : N - 1 - p)];
-        sr += av * v.re;
-        si += av * v.im;
+    // fold the extension region back onto the 2d matching points (transpose
+    // of the continuation): column c of the continuation matrix
+    for (int t = tid; t < kLP * 2 * dd; t += NTH) {
+      const int l = t / (2 * dd), c = t % (2 * dd);
+      double sr = 0.0, si = 0.0;
+#pragma unroll 4
+      for (int p = 0; p < CE; ++p) {
+        const double mv = Mx[p * 2 * dd + c];
+        const cx<double> y = buf[l * LSZ + ph(n + p)];
+        sr += mv * y.re;
+        si += mv * y.im;
       }
-      cs[(l * 2 + end) * kMaxFcD + j] = {sr, si};
-    }
-    __syncthreads();
-    for (int t = lane; t < kLP * 2 * dd; t += 64) {
-      const int l = t / (2 * dd), rem = t % (2 * dd), end = rem / dd, k = rem % dd;
-      double sr = 0, si = 0;
-#pragma unroll
-      for (int j = 0; j < kMaxFcD; ++j) {
-        if (j < dd) {
-          const double qv = Qs[k * dd + j];
-          const cx<double> c = cs[(l * 2 + end) * kMaxFcD + j];
-          sr += qv * c.re;
-          si += qv * c.im;
-        }
-      }
-      gs[(l * 2 + end) * kMaxFcD + k] = {sr, si};
+      fold[l * 2 * kMaxFcD + c] = {sr, si};
     }
     __syncthreads();
   }
@@ -291,30 +276,31 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
   for (int r = 0; r < 4; ++r) c4[r] = ADJ ? 1.0 : -a.coef[d.dir][d.s0 + r];
   T* out = a.out[d.dir] + d.base;
   const int64_t ls = a.line_stride[d.dir], ps = a.pt_stride[d.dir];
+  constexpr int TMAX = (2 * N + NTH - 1) / NTH;
 #pragma unroll
   for (int t = 0; t < TMAX; ++t) {
-    const int e = lane + 64 * t, it = e & 1, i = e >> 1;
+    const int e = tid + NTH * t, it = e & 1, i = e >> 1;
     if (i < n && (it == 0 || d.has1)) {
       const cx<double> z0 = buf[(2 * it) * LSZ + ph(i)], z1 = buf[(2 * it + 1) * LSZ + ph(i)];
       double dv[4] = {z0.re, z0.im, z1.re, z1.im};
       if (ADJ) {
         if (i >= n - dd) {
-          const int k = i - (n - dd);
-          const cx<double> ga = gs[((2 * it) * 2 + 1) * kMaxFcD + k], gb = gs[((2 * it + 1) * 2 + 1) * kMaxFcD + k];
-          dv[0] += ga.re; dv[1] += ga.im; dv[2] += gb.re; dv[3] += gb.im;
+          const cx<double> f0 = fold[(2 * it) * 2 * kMaxFcD + (i - (n - dd))];
+          const cx<double> f1 = fold[(2 * it + 1) * 2 * kMaxFcD + (i - (n - dd))];
+          dv[0] += f0.re; dv[1] += f0.im; dv[2] += f1.re; dv[3] += f1.im;
         }
         if (i < dd) {
-          const int k = dd - 1 - i;
-          const cx<double> ga = gs[((2 * it) * 2 + 0) * kMaxFcD + k], gb = gs[((2 * it + 1) * 2 + 0) * kMaxFcD + k];
-          dv[0] += ga.re; dv[1] += ga.im; dv[2] += gb.re; dv[3] += gb.im;
+          const cx<double> f0 = fold[(2 * it) * 2 * kMaxFcD + dd + (dd - 1 - i)];
+          const cx<double> f1 = fold[(2 * it + 1) * 2 * kMaxFcD + dd + (dd - 1 - i)];
+          dv[0] += f0.re; dv[1] += f0.im; dv[2] += f1.re; dv[3] += f1.im;
         }
       }
-      T* p = out + it * ls + (int64_t)i * ps;
+      T* q = out + it * ls + (int64_t)i * ps;
       if constexpr (sizeof(T) == 8) {
-        reinterpret_cast<double2*>(p)[0] = make_double2(c4[0] * dv[0], c4[1] * dv[1]);
-        reinterpret_cast<double2*>(p)[1] = make_double2(c4[2] * dv[2], c4[3] * dv[3]);
+        reinterpret_cast<double2*>(q)[0] = make_double2(c4[0] * dv[0], c4[1] * dv[1]);
+        reinterpret_cast<double2*>(q)[1] = make_double2(c4[2] * dv[2], c4[3] * dv[3]);
       } else {
-        *reinterpret_cast<float4*>(p) =
+        *reinterpret_cast<float4*>(q) =
             make_float4(float(c4[0] * dv[0]), float(c4[1] * dv[1]), float(c4[2] * dv[2]), float(c4[3] * dv[3]));
       }
     }
@@ -322,93 +308,98 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
 }
 
 // Issue the loads of the FC tables into registers (kept until staged).
-template <int N>
+template <int N, int NTH>
 struct TabRegs {
-  static constexpr int RT = (2 * N + 63) / 64, MT = (N + 63) / 64, QT = kFcTab / 64;
-  double rr[RT], mm[MT], qq[QT];
+  static constexpr int RT = (N + NTH - 1) / NTH, MT = (N + NTH - 1) / NTH, XT = (kFcTab + NTH - 1) / NTH;
+  double rr[RT][2], mm[MT], xx[XT];
   __device__ __forceinline__ void load(const FcPlanDev& fc, int lane) {
-    const int dd = fc.d, nqa = fc.d * fc.d + fc.C * fc.d;
+    const int nmx = 2 * fc.d * (fc.C + fc.E);
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
-      const int k = lane + 64 * t;
-      rr[t] = (k < 2 * N) ? fc.roots[k] : 0.0;
+      const int k = lane + NTH * t;
+      rr[t][0] = (k < N) ? fc.roots[2 * k] : 0.0;
+      rr[t][1] = (k < N) ? fc.roots[2 * k + 1] : 0.0;
     }
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      const int k = lane + 64 * t;
+      const int k = lane + NTH * t;
       mm[t] = (k < N) ? fc.mu[k] : 0.0;
     }
 #pragma unroll
-    for (int t = 0; t < QT; ++t) {
-      const int k = lane + 64 * t;
-      qq[t] = (k < dd * dd) ? fc.Q[k] : ((k < nqa) ? fc.A[k - dd * dd] : 0.0);
+    for (int t = 0; t < XT; ++t) {
+      const int k = lane + NTH * t;
+      xx[t] = (k < nmx) ? fc.Mx[k] : 0.0;
     }
   }
-  __device__ __forceinline__ void stage(double* roots, double* mu, double* qa, int lane) const {
+  __device__ __forceinline__ void stage(cx<double>* roots, double* mu, double* Mx, int nmx, int lane) const {
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
-      const int k = lane + 64 * t;
-      if (k < 2 * N) roots[k] = rr[t];
+      const int k = lane + NTH * t;
+      if (k < N) roots[rix(k)] = {rr[t][0], rr[t][1]};
     }
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      const int k = lane + 64 * t;
+      const int k = lane + NTH * t;
       if (k < N) mu[k] = mm[t];
     }
 #pragma unroll
-    for (int t = 0; t < QT; ++t) qa[lane + 64 * t] = qq[t];
+    for (int t = 0; t < XT; ++t) {
+      const int k = lane + NTH * t;
+      if (k < nmx) Mx[k] = xx[t];
+    }
   }
 };
 
-// UPW = 2: the wave's two units and the tables are all loaded before the
-// first transform.  UPW = 1 (long lines, whose loads alone would fill the
-// register file): tables first, then the unit in chunks of 8 load slots.
-template <typename T, bool ADJ, int N1, int N2, int UPW>
-__global__ __launch_bounds__(64) void lines4_kernel(Lines4Args<T> a) {
+// A workgroup of NW waves (NTH = 64 NW threads) transforms one unit at a
+// time.  UPW = 2: the workgroup's two units and the tables are all loaded
+// before the first transform.  UPW = 1 (also for long lines, whose loads alone
+// would fill the register file): tables first, then the unit in chunks of
+// 8 load slots per thread.
+template <typename T, bool ADJ, int N1, int N2, int UPW, int NW>
+__global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
   constexpr int N = N1 * N2;
-  constexpr int TMAX = (2 * N + 63) / 64;
+  constexpr int NTH = 64 * NW;
+  constexpr int TMAX = (2 * N + NTH - 1) / NTH;
   typedef L4Smem<N1, N2> SM;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sm = reinterpret_cast<double*>(smem_raw);
   cx<double>* buf = reinterpret_cast<cx<double>*>(sm);
-  cx<double>* cs = reinterpret_cast<cx<double>*>(sm + SM::BUF);
-  double* roots = sm + SM::BUF + SM::CS;
-  double* mu = roots + SM::ROOTS;
-  double* qa = mu + SM::MU;
+  cx<double>* fold = reinterpret_cast<cx<double>*>(sm + SM::BUF);
+  cx<double>* roots = reinterpret_cast<cx<double>*>(sm + SM::BUF + SM::FOLD);
+  double* mu = sm + SM::BUF + SM::FOLD + SM::ROOTS;
+  double* Mx = mu + SM::MU;
 
   const FcPlanDev& fc = a.fc;
-  const int n = fc.n, dd = fc.d, C = fc.C, E = fc.E;
-  const int lane = threadIdx.x;
-  const double* Qs = qa;
-  const double* As = qa + dd * dd;
+  const int n = fc.n, dd = fc.d, CE = fc.C + fc.E;
+  const int tid = threadIdx.x;
 
   if constexpr (UPW == 2) {
     const UnitDesc d0 = decode_unit(a, 2 * (int)blockIdx.x);
     const UnitDesc d1 = decode_unit(a, 2 * (int)blockIdx.x + 1);
     UnitRegs<T, TMAX> R0, R1;
-    load_unit(a, d0, n, lane, R0);
-    load_unit(a, d1, n, lane, R1);
-    TabRegs<N> tab;
-    tab.load(fc, lane);
-    tab.stage(roots, mu, qa, lane);
+    load_unit<T, TMAX, NTH>(a, d0, n, tid, R0);
+    load_unit<T, TMAX, NTH>(a, d1, n, tid, R1);
+    TabRegs<N, NTH> tab;
+    tab.load(fc, tid);
+    tab.stage(roots, mu, Mx, 2 * dd * CE, tid);
     if (d0.live) {
-      stage_unit<T, TMAX, N1, N2>(R0, d0, a.coef[d0.dir], ADJ, n, lane, buf);
+      stage_unit<T, TMAX, N1, N2, NTH>(R0, d0, a.coef[d0.dir], ADJ, n, tid, buf);
       __syncthreads();
-      transform_unit<T, ADJ, TMAX, N1, N2>(a, d0, n, dd, C, E, lane, buf, cs, roots, mu, Qs, As);
+      transform_unit<T, ADJ, N1, N2, NTH>(a, d0, n, dd, CE, tid, buf, fold, roots, mu, Mx);
     }
     if (d1.live) {
       __syncthreads();
-      stage_unit<T, TMAX, N1, N2>(R1, d1, a.coef[d1.dir], ADJ, n, lane, buf);
+      stage_unit<T, TMAX, N1, N2, NTH>(R1, d1, a.coef[d1.dir], ADJ, n, tid, buf);
       __syncthreads();
-      transform_unit<T, ADJ, TMAX, N1, N2>(a, d1, n, dd, C, E, lane, buf, cs, roots, mu, Qs, As);
+      transform_unit<T, ADJ, N1, N2, NTH>(a, d1, n, dd, CE, tid, buf, fold, roots, mu, Mx);
     }
   } else {
     const UnitDesc d0 = decode_unit(a, (int)blockIdx.x);
     if (!d0.live) return;
     {
-      TabRegs<N> tab;
-      tab.load(fc, lane);
-      tab.stage(roots, mu, qa, lane);
+      TabRegs<N, NTH> tab;
+      tab.load(fc, tid);
+      tab.stage(roots, mu, Mx, 2 * dd * CE, tid);
     }
     constexpr int CH = 8;
     for (int c0 = 0; c0 < TMAX; c0 += CH) {
@@ -417,7 +408,7 @@ __global__ __launch_bounds__(64) void lines4_kernel(Lines4Args<T> a) {
       const int64_t ls = a.line_stride[d0.dir], ps = a.pt_stride[d0.dir];
 #pragma unroll
       for (int t = 0; t < CH; ++t) {
-        const int e = lane + 64 * (c0 + t), it = e & 1, i = e >> 1;
+        const int e = tid + NTH * (c0 + t), it = e & 1, i = e >> 1;
         if (c0 + t < TMAX && i < n && (it == 0 || d0.has1)) {
           const T* p = in + it * ls + (int64_t)i * ps;
           if constexpr (sizeof(T) == 8) {
@@ -434,29 +425,27 @@ __global__ __launch_bounds__(64) void lines4_kernel(Lines4Args<T> a) {
         }
       }
       const double* cf = a.coef[d0.dir];
-      constexpr int PS = N2 + 1, LSZ = N1 * PS;
 #pragma unroll
       for (int t = 0; t < CH; ++t) {
-        const int e = lane + 64 * (c0 + t), it = e & 1, i = e >> 1;
+        const int e = tid + NTH * (c0 + t), it = e & 1, i = e >> 1;
         if (c0 + t < TMAX && i < n) {
-          const int ph = (i / N2) * PS + i % N2;
+          const int ph = (i / N2) * SM::PS + i % N2;
           const double f0 = ADJ ? cf[d0.s0] : 1.0, f1 = ADJ ? cf[d0.s0 + 1] : 1.0;
           const double f2 = ADJ ? cf[d0.s0 + 2] : 1.0, f3 = ADJ ? cf[d0.s0 + 3] : 1.0;
-          buf[(2 * it) * LSZ + ph] = {f0 * (double)R.v[t][0], f1 * (double)R.v[t][1]};
-          buf[(2 * it + 1) * LSZ + ph] = {f2 * (double)R.v[t][2], f3 * (double)R.v[t][3]};
+          buf[(2 * it) * SM::LSZ + ph] = {f0 * (double)R.v[t][0], f1 * (double)R.v[t][1]};
+          buf[(2 * it + 1) * SM::LSZ + ph] = {f2 * (double)R.v[t][2], f3 * (double)R.v[t][3]};
         }
       }
     }
     if (ADJ) {
-      constexpr int PS = N2 + 1, LSZ = N1 * PS;
       const int ext = N - n;
-      for (int e = lane; e < kLP * ext; e += 64) {
+      for (int e = tid; e < kLP * ext; e += NTH) {
         const int l = e / ext, i = n + e % ext;
-        buf[l * LSZ + (i / N2) * PS + i % N2] = {0.0, 0.0};
+        buf[l * SM::LSZ + (i / N2) * SM::PS + i % N2] = {0.0, 0.0};
       }
     }
     __syncthreads();
-    transform_unit<T, ADJ, TMAX, N1, N2>(a, d0, n, dd, C, E, lane, buf, cs, roots, mu, Qs, As);
+    transform_unit<T, ADJ, N1, N2, NTH>(a, d0, n, dd, CE, tid, buf, fold, roots, mu, Mx);
   }
 }
 
@@ -471,25 +460,40 @@ bool fourstep_split(int Np, int* n1, int* n2) {
   }
 }
 
-template <typename T, bool ADJ, int N1, int N2>
-static hipError_t go(const Lines4Args<T>& a, hipStream_t s) {
-  if (L4Smem<N1, N2>::bytes > kLines4MaxLds) return hipErrorNotSupported;
-  constexpr int UPW = (2 * N1 * N2 + 63) / 64 <= 9 ? 2 : 1;
-  const int waves = (a.nunits + UPW - 1) / UPW;
-  if (waves == 0) return hipSuccess;
-  const size_t sh = L4Smem<N1, N2>::bytes;
-  hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, UPW>), dim3((unsigned)waves), dim3(64), sh, s, a);
+// Two units per workgroup only where both units' loads fit in registers.
+template <int N1, int N2, int NW>
+constexpr bool kPairOk = (2 * N1 * N2 + 64 * NW - 1) / (64 * NW) <= 9;
+
+template <typename T, bool ADJ, int N1, int N2, int NW>
+static hipError_t go_nw(const Lines4Args<T>& a, int upw, size_t sh, hipStream_t s) {
+  if constexpr (kPairOk<N1, N2, NW>) {
+    if (upw == 2) {
+      const int groups = (a.nunits + 1) / 2;
+      if (groups == 0) return hipSuccess;
+      hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, 2, NW>), dim3((unsigned)groups), dim3(64 * NW), sh, s, a);
+      return hipGetLastError();
+    }
+  }
+  if (a.nunits == 0) return hipSuccess;
+  hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, 1, NW>), dim3((unsigned)a.nunits), dim3(64 * NW), sh, s, a);
   return hipGetLastError();
 }
 
+template <typename T, bool ADJ, int N1, int N2>
+static hipError_t go(const Lines4Args<T>& a, int upw, int nw, hipStream_t s) {
+  const size_t sh = L4Smem<N1, N2>::bytes(2 * a.fc.d * (a.fc.C + a.fc.E));
+  if (sh > kLines4MaxLds) return hipErrorNotSupported;
+  return nw == 2 ? go_nw<T, ADJ, N1, N2, 2>(a, upw, sh, s) : go_nw<T, ADJ, N1, N2, 1>(a, upw, sh, s);
+}
+
 template <typename T, bool ADJ>
-static hipError_t by_size(const Lines4Args<T>& a, hipStream_t s) {
+static hipError_t by_size(const Lines4Args<T>& a, int upw, int nw, hipStream_t s) {
   switch (a.fc.Np) {
-    case 90: return go<T, ADJ, 9, 10>(a, s);
-    case 160: return go<T, ADJ, 16, 10>(a, s);
-    case 288: return go<T, ADJ, 16, 18>(a, s);
-    case 540: return go<T, ADJ, 20, 27>(a, s);
-    case 1080: return go<T, ADJ, 30, 36>(a, s);
+    case 90: return go<T, ADJ, 9, 10>(a, upw, nw, s);
+    case 160: return go<T, ADJ, 16, 10>(a, upw, nw, s);
+    case 288: return go<T, ADJ, 16, 18>(a, upw, nw, s);
+    case 540: return go<T, ADJ, 20, 27>(a, upw, nw, s);
+    case 1080: return go<T, ADJ, 30, 36>(a, upw, nw, s);
     default: return hipErrorNotSupported;
   }
 }
@@ -521,7 +525,8 @@ static hipError_t launch4_t(const Plan& p, const LineLaunch& L, hipStream_t s) {
   const int64_t per = p.Nq * p.G;
   a.units_first = (int)(per * a.npe[a.dir_first]);
   a.nunits = a.units_first + ((dx && dy) ? (int)(per * a.npe[1]) : 0);
-  return L.mode == LINE_ADJ ? by_size<T, true>(a, s) : by_size<T, false>(a, s);
+  const int upw = p.sched.line_units_per_wave, nw = p.sched.line_waves_per_unit;
+  return L.mode == LINE_ADJ ? by_size<T, true>(a, upw, nw, s) : by_size<T, false>(a, upw, nw, s);
 }
 
 hipError_t launch_lines4(const Plan& p, const LineLaunch& L, hipStream_t s) {

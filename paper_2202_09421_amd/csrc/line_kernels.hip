@@ -252,7 +252,7 @@ hipError_t launch_line_generic(const Plan& p, const void* in, void* out, int mod
 // Both line sets: one four-step launch when the x and y plans coincide,
 // otherwise one launch per direction (four-step where N_p has a split).
 hipError_t launch_lines(const Plan& p, const LineLaunch& L, hipStream_t s) {
-  const bool four_x = p.fcx.n1 > 0, four_y = p.fcy.n1 > 0;
+  const bool four_x = p.fcx.n1 > 0 && !p.sched.line_generic, four_y = p.fcy.n1 > 0 && !p.sched.line_generic;
   if (L.dirs == 3 && p.fc_same && four_x) {
     const hipError_t e = launch_lines4(p, L, s);
     if (e != hipErrorNotSupported) return e;

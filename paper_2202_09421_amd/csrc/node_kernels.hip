@@ -148,7 +148,7 @@ struct NodeFwdArgs {
 
 // L_out may alias L3: each element is read and then written by one lane.
 template <typename T, int RTC>
-__global__ __launch_bounds__(RTC == 0 ? 1024 : (RTC == 3 ? 192 : 256)) void node_fwd_kernel(NodeFwdArgs<T> a) {
+__global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwdArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const NodeGeom& G = a.geo;
   const TileLane t = tile_lane(G);
@@ -269,7 +269,7 @@ struct NodeAdjArgs {
 
 // ap1 is read (P1^{n+1}) and overwritten (P1^n) element by element by one lane.
 template <typename T, int RTC>
-__global__ __launch_bounds__(RTC == 0 ? 1024 : (RTC == 3 ? 192 : 256)) void node_adj_kernel(NodeAdjArgs<T> a) {
+__global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const NodeGeom& G = a.geo;
   const TileLane t = tile_lane(G);
@@ -387,11 +387,22 @@ static NodeGeom make_geom(const Plan& p) {
   g.M = (int)p.M; g.Mpad = (int)p.Mpad; g.G = (int)p.G;
   g.nb = (int)p.nb; g.npos = (int)p.npos; g.K1 = (int)(p.K + 1);
   g.RT = (int)(p.Mpad / 16);
-  g.NT = (g.RT <= 4 && 4 % g.RT == 0) ? 4 / g.RT : 1;
+  g.NT = p.sched.node_tiles_per_block;
   g.npos_total = (int)(p.ny * p.nxp);
   g.grp_stride = p.grp_stride;
   g.inst_stride = p.inst_stride;
   return g;
+}
+
+bool node_tiles_ok(const Plan& p, int nt) {
+  const int rt = (int)(p.Mpad / 16);
+  if (rt > 4) return nt == 1;
+  return (nt == 1 || nt == 2 || nt == 4) && nt * rt <= 8;
+}
+
+int node_tiles_default(const Plan& p) {
+  const int rt = (int)(p.Mpad / 16);
+  return (rt <= 4 && 4 % rt == 0) ? 4 / rt : 1;
 }
 
 static size_t node_shmem(const NodeGeom& g, size_t es) {

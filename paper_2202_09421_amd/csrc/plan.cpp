@@ -159,7 +159,24 @@ static bool build_fc(const rte_problem& pb, int n, double h, std::vector<double>
     buf.push_back(std::cos(ang));
     buf.push_back(std::sin(ang));
   }
-  if (!fourstep_split(Np, &fc.n1, &fc.n2) || d * d + C * d > kFcTab) fc.n1 = fc.n2 = 0;
+  // continuation matrix (Sec. 4.3 steps 1-4 as one linear map): extension
+  // value p (0 <= p < C + E) = sum_k MR[p][k] g[n-d+k] + sum_k ML[p][k] g[d-1-k]
+  // with MR[p][k] = sum_j A[p][j] Q[k][j] (p < C) and
+  //      ML[p][k] = sum_j A[C+E-1-p][j] Q[k][j] (p >= E); row p = [MR | ML]
+  offs.push_back(buf.size());
+  const int CE = C + E;
+  for (int p = 0; p < CE; ++p) {
+    for (int side = 0; side < 2; ++side)
+      for (int k = 0; k < d; ++k) {
+        long double acc = 0.0L;
+        const int row = side == 0 ? p : CE - 1 - p;
+        const bool on = side == 0 ? (p < C) : (p >= E);
+        if (on)
+          for (int j = 0; j < d; ++j) acc += (long double)pb.fc_A[row * d + j] * (long double)pb.fc_Q[k * d + j];
+        buf.push_back((double)acc);
+      }
+  }
+  if (!fourstep_split(Np, &fc.n1, &fc.n2) || CE > 64 || 2 * d * CE > kFcTab) fc.n1 = fc.n2 = 0;
   return true;
 }
 
@@ -417,6 +434,7 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
     return RTE_EUNSUPPORTED;
   }
 
+  p.sched.node_tiles_per_block = node_tiles_default(p);
   p.fc_same = p.fcx.n == p.fcy.n && p.fcx.Np == p.fcy.Np && p.fcx.E == p.fcy.E &&
               std::equal(fcbuf.begin() + ox[1], fcbuf.begin() + ox[2], fcbuf.begin() + oy[1]);
 
@@ -435,6 +453,8 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
   const double* fb = p.dev.fc_buf;
   p.fcx.tw = fb + ox[0]; p.fcx.mu = fb + ox[1]; p.fcx.Q = fb + ox[2]; p.fcx.A = fb + ox[3]; p.fcx.roots = fb + ox[4];
   p.fcy.tw = fb + oy[0]; p.fcy.mu = fb + oy[1]; p.fcy.Q = fb + oy[2]; p.fcy.A = fb + oy[3]; p.fcy.roots = fb + oy[4];
+  p.fcx.Mx = fb + ox[5];
+  p.fcy.Mx = fb + oy[5];
   *out = reinterpret_cast<rte_plan*>(P);
   return RTE_OK;
 }

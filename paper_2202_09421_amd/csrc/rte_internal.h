@@ -15,7 +15,7 @@ constexpr int kGroup = 4;        // ordinate slots per storage group (one reflec
 constexpr int kMaxPasses = 12;   // FFT passes (radices 2,3,4,5)
 constexpr int kMaxFcD = 8;       // matching points supported
 constexpr int kLineThreads = 128; // generic (Stockham) line kernel
-constexpr int kFcTab = 256;      // Q (d*d) and A (C*d) entries staged by the four-step kernel
+constexpr int kFcTab = 384;      // continuation matrix entries ((C+E) * 2d) staged by the four-step kernel
 
 void set_error(const std::string& msg);
 const char* last_error();
@@ -38,6 +38,7 @@ struct FcPlanDev {
   const double* A;          // C*d
   int n1, n2;               // four-step split Np = n1 * n2 (0: generic Stockham kernel)
   const double* roots;      // Np complex roots exp(-2 pi i e / Np), interleaved
+  const double* Mx;         // (C+E) x 2d continuation matrix [MR | ML] (four-step kernel)
 };
 
 // Four-step splits with register codelets (Np -> n1 x n2); 0 if none.
@@ -87,6 +88,8 @@ struct Plan {
   int64_t grp_stride = 0;   // ny * nxp * kGroup elements
   int64_t inst_stride = 0;  // G * grp_stride
   bool fc_same = false;     // x and y FC plans identical: both line sets in one launch
+  rte_schedule sched{2, 0, 0, 1};  // launch schedule (node_tiles_per_block resolved at create)
+  int64_t sched_version = 0;       // bumped by every schedule change (graph keys)
   int64_t nb = 0;     // boundary nodes 2(nx+ny)-4
   int64_t npos = 0;   // max(nx, ny)
   std::vector<int> slot_m;  // slot -> ordinate index
@@ -101,6 +104,7 @@ struct Plan {
   hipGraphExec_t gexec = nullptr;
   const void* gkey[9] = {nullptr};
   int64_t gkey_bytes = 0;
+  int64_t gkey_sched = -1;
   // instrumentation: event pairs per kernel class
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -195,6 +199,9 @@ struct NodeAdjLaunch {
   int step;            // n
 };
 hipError_t launch_node_adj(const Plan& p, const NodeAdjLaunch& L, hipStream_t s);
+// admissible node tiles per block for this plan (RT = Mpad / 16 row tiles)
+bool node_tiles_ok(const Plan& p, int nt);
+int node_tiles_default(const Plan& p);
 
 hipError_t launch_detect(const Plan& p, const double* flux, double* G, int K, hipStream_t s);
 hipError_t launch_inject(const Plan& p, const double* Gbar, double* inj, int K, hipStream_t s);

@@ -15,6 +15,7 @@ theta, sigma_x, sigma_theta, tau, sigma_t, t0, group) and a list
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -56,6 +57,15 @@ class rte_detector(ctypes.Structure):
     _fields_ = [("x", ctypes.c_double), ("y", ctypes.c_double), ("sigma_d", ctypes.c_double)]
 
 
+class rte_schedule(ctypes.Structure):
+    _fields_ = [("line_units_per_wave", ctypes.c_int32), ("line_generic", ctypes.c_int32),
+                ("node_tiles_per_block", ctypes.c_int32), ("line_waves_per_unit", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"line_units_per_wave": self.line_units_per_wave, "line_generic": self.line_generic,
+                "node_tiles_per_block": self.node_tiles_per_block, "line_waves_per_unit": self.line_waves_per_unit}
+
+
 _lib = None
 
 
@@ -82,10 +92,15 @@ def lib():
         L.rte_batch_gradient.argtypes = [vp, pp, pp, pp, pp, pp, pp, pp, pp, ctypes.POINTER(i64), vp]
         L.rte_profile_enable.argtypes = [vp, ctypes.c_int]
         L.rte_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+        sp = ctypes.POINTER(rte_schedule)
+        L.rte_plan_get_schedule.argtypes = [vp, sp]
+        L.rte_plan_set_schedule.argtypes = [vp, sp]
+        L.rte_plan_autotune.argtypes = [vp, vp, vp, vp, i64, vp, sp]
         L.rte_last_error.restype = ctypes.c_char_p
         for f in ("rte_plan_create", "rte_plan_destroy", "rte_plan_info", "rte_workspace_bytes", "rte_forward",
                   "rte_adjoint", "rte_gradient", "rte_profile_enable", "rte_profile_read", "rte_plan_set_graph",
-                  "rte_batch_create", "rte_batch_destroy", "rte_batch_gradient"):
+                  "rte_batch_create", "rte_batch_destroy", "rte_batch_gradient", "rte_plan_get_schedule",
+                  "rte_plan_set_schedule", "rte_plan_autotune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -206,6 +221,61 @@ class Plan:
         _check(lib().rte_adjoint(self._h, _ptr(a), _ptr(b), _ptr(gbar), _ptr(da), _ptr(db), _ptr(ws), ws.numel(),
                                  _stream()))
         return da, db
+
+    def schedule(self):
+        """Current launch schedule (dict)."""
+        sc = rte_schedule()
+        _check(lib().rte_plan_get_schedule(self._h, ctypes.byref(sc)))
+        return sc.as_dict()
+
+    def set_schedule(self, sched):
+        sc = rte_schedule(int(sched.get("line_units_per_wave", 0)), int(sched.get("line_generic", 0)),
+                          int(sched.get("node_tiles_per_block", 0)), int(sched.get("line_waves_per_unit", 0)))
+        _check(lib().rte_plan_set_schedule(self._h, ctypes.byref(sc)))
+
+    def tune_key(self):
+        sp = self.spec
+        dev = torch.cuda.get_device_name(self.device) if torch.cuda.is_available() else "none"
+        return "%s|%s|nx%d|ny%d|M%d|Nq%d|Np%d,%d" % (dev, "f64" if self.dtype == torch.float64 else "f32",
+                                                     sp.Nx + 1, sp.Ny + 1, sp.M, self.Nq, self.Np_x, self.Np_y)
+
+    def autotune(self, mu_a, mu_s, cache=None):
+        """Pick the fastest launch schedule for this plan's shapes with the
+        library's autotuner (rte_plan_autotune) and apply it.  `cache`: a JSON
+        file of earlier choices keyed by device and shapes (default
+        $RTE_TUNE_CACHE or ~/.cache/rte_fcdom/schedules.json; False disables);
+        a hit applies the stored schedule without timing."""
+        path = None
+        if cache is not False:
+            path = cache or os.environ.get("RTE_TUNE_CACHE") or os.path.join(
+                os.path.expanduser("~"), ".cache", "rte_fcdom", "schedules.json")
+        key = self.tune_key()
+        table = {}
+        if path and os.path.exists(path):
+            try:
+                with open(path) as fh:
+                    table = json.load(fh)
+            except (OSError, ValueError):
+                table = {}
+        if key in table:
+            self.set_schedule(table[key])
+            return dict(table[key], cached=True)
+        a, b = self._medium(mu_a, mu_s)
+        ws = self.workspace(True)
+        sc = rte_schedule()
+        _check(lib().rte_plan_autotune(self._h, _ptr(a), _ptr(b), _ptr(ws), ws.numel(), _stream(), ctypes.byref(sc)))
+        chosen = sc.as_dict()
+        if path:
+            try:
+                os.makedirs(os.path.dirname(path), exist_ok=True)
+                table[key] = chosen
+                tmp = path + ".tmp%d" % os.getpid()
+                with open(tmp, "w") as fh:
+                    json.dump(table, fh, indent=1, sort_keys=True)
+                os.replace(tmp, path)
+            except OSError:
+                pass
+        return dict(chosen, cached=False)
 
     def set_graph(self, on=True):
         """Graph mode: rte_gradient is recorded once per argument set and

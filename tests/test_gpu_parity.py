@@ -91,7 +91,13 @@ CASES = [
     dict(N=40, M=20, K=15, seed=5, g=0.8),
     dict(N=64, M=32, K=12, seed=6, n_in=1.4, g=0.9),
     dict(N=30, M=16, K=1, seed=7),                          # a single step
+    dict(N=16, M=48, K=10, seed=8, n_in=1.4),               # 3 row tiles of 16 slots
+    dict(N=14, M=64, K=8, seed=9, n_in=1.4, g=0.9),         # 4 row tiles
+    dict(N=12, M=80, K=6, seed=10, n_in=1.33),              # 5 row tiles (runtime tile count)
+    dict(N=64, M=16, K=10, seed=11, Ny=20, n_in=1.4),       # four-step x lines, generic y lines
+    dict(N=128, M=8, K=6, seed=12, n_in=1.4),               # N_p = 160 (16 x 10 split)
 ]
+GRAD_CASES = [0, 1, 2, 3, 4, 5, 7, 8, 9, 10]
 
 
 def _spec(case):
@@ -114,7 +120,7 @@ def test_forward_fp64_matches_oracle(rte, case):
     assert rel(uK.cpu(), uK_o) < TOL64, rel(uK.cpu(), uK_o)
 
 
-@pytest.mark.parametrize("case", CASES[:6], ids=[str(i) for i in range(6)])
+@pytest.mark.parametrize("case", [CASES[i] for i in GRAD_CASES], ids=[str(i) for i in GRAD_CASES])
 def test_gradient_fp64_matches_oracle(rte, case):
     spec = _spec(case)
     say("gradient fp64", case)
