@@ -41,6 +41,15 @@ struct Lines4Args {
 };
 
 constexpr int kLP = 4;  // complex lines per unit (two lines x slot pairs)
+
+// One unit per workgroup: workgroup b runs on XCD b % 8, so units 2x and
+// 2x + 1 of each chunk of 16 (the two column pairs of one 128-byte row
+// segment) go to workgroups b and b + 8 of that chunk, i.e. to one XCD and
+// its L2.
+__device__ __forceinline__ int remap_unit16(int b) {
+  const int chunk = b >> 4, x = b & 7, h = (b >> 3) & 1;
+  return chunk * 16 + 2 * x + h;
+}
 constexpr size_t kLines4MaxLds = 64 * 1024;
 
 // thread-owned loads of one unit: point i of line it (0/1) for
@@ -394,7 +403,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
       transform_unit<T, ADJ, N1, N2, NTH>(a, d1, n, dd, CE, tid, buf, fold, roots, mu, Mx);
     }
   } else {
-    const UnitDesc d0 = decode_unit(a, (int)blockIdx.x);
+    const UnitDesc d0 = decode_unit(a, remap_unit16((int)blockIdx.x));
     if (!d0.live) return;
     {
       TabRegs<N, NTH> tab;
@@ -475,7 +484,8 @@ static hipError_t go_nw(const Lines4Args<T>& a, int upw, size_t sh, hipStream_t 
     }
   }
   if (a.nunits == 0) return hipSuccess;
-  hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, 1, NW>), dim3((unsigned)a.nunits), dim3(64 * NW), sh, s, a);
+  const int groups = ((a.nunits + 15) / 16) * 16;
+  hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, 1, NW>), dim3((unsigned)groups), dim3(64 * NW), sh, s, a);
   return hipGetLastError();
 }
 

@@ -65,6 +65,7 @@ struct Mfma<float> {
 // for RT >= 5 (NT = 1).
 struct NodeGeom {
   int nx, ny, nxp, M, Mpad, G, nb, npos, K1, RT, NT, npos_total;
+  int ntiles, tile_shift;   // tiles are visited from the one holding the last row's start
   int64_t grp_stride, inst_stride;
 };
 
@@ -98,7 +99,11 @@ __device__ __forceinline__ TileLane tile_lane(const NodeGeom& G) {
   t.r = lane >> 4;
   t.rt = wave % G.RT;
   t.nt = wave / G.RT;
-  t.P = ((int)blockIdx.x * G.NT + t.nt) * 16 + t.node;
+  // the first and last rows are all boundary nodes, whose waves take longer:
+  // visit the last row first so that it does not trail the grid
+  int tile = (int)blockIdx.x * G.NT + t.nt;
+  tile = (tile < G.ntiles) ? (tile + G.tile_shift) % G.ntiles : G.ntiles;
+  t.P = tile * 16 + t.node;
   t.j = t.P / G.nxp;
   t.i = t.P - t.j * G.nxp;
   t.valid = (t.P < G.npos_total) && (t.i < G.nx);
@@ -122,6 +127,18 @@ __device__ __forceinline__ typename Mfma<T>::acc_t scatter_tile(const T* Bs, con
       acc = Mfma<T>::step(T(Wt[(4 * ks + t.r) * G.Mpad + col]), Bs[(4 * ks + t.r) * 16 + t.node], acc);
   }
   return acc;
+}
+
+// Element access at a 32-bit byte offset from a per-block base pointer: the
+// base stays in scalar registers and one offset register serves every array
+// (one instance of a state is below 4 GiB; checked by the plan).
+template <typename T>
+__device__ __forceinline__ T ldo(const T* base, uint32_t boff) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T* base, uint32_t boff, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
 }
 
 template <typename T, int RTC>
@@ -157,18 +174,26 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
   const int q = blockIdx.y;
   const int64_t ib = (int64_t)q * G.inst_stride;
 
+  const T* uq = a.u + ib;
+  const T* Xq = a.X + ib;
+  const T* Yq = a.Y + ib;
+  const T* L1q = a.L1 + ib;
+  const T* L2q = a.L2 + ib;
+  const T* L3q = a.L3 + ib;
+  T* uoq = a.u_out + ib;
+  T* Loq = a.L_out + ib;
   T u[4], X[4], Y[4], L1[4], L2[4], L3[4];
-  int64_t off[4];
+  uint32_t off[4];
   bool gv[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int g = 4 * t.rt + v;
     gv[v] = t.valid && g < G.G;
-    off[v] = ib + (int64_t)g * G.grp_stride + (int64_t)t.P * kGroup + t.r;
+    off[v] = (uint32_t)(((uint32_t)g * (uint32_t)G.grp_stride + (uint32_t)t.P * kGroup + t.r) * sizeof(T));
     u[v] = X[v] = Y[v] = L1[v] = L2[v] = L3[v] = T(0);
     if (gv[v]) {
-      u[v] = a.u[off[v]]; X[v] = a.X[off[v]]; Y[v] = a.Y[off[v]];
-      L1[v] = a.L1[off[v]]; L2[v] = a.L2[off[v]]; L3[v] = a.L3[off[v]];
+      u[v] = ldo(uq, off[v]); X[v] = ldo(Xq, off[v]); Y[v] = ldo(Yq, off[v]);
+      L1[v] = ldo(L1q, off[v]); L2[v] = ldo(L2q, off[v]); L3[v] = ldo(L3q, off[v]);
     }
   }
   const int gn = t.j * G.nx + t.i;
@@ -188,52 +213,59 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
   for (int v = 0; v < 4; ++v) {
     const T Ln = B * S[v] - (A + B) * u[v] + X[v] + Y[v];
     un[v] = u[v] + cdt * (T(kChi0) * Ln + T(kChi1) * L1[v] + T(kChi2) * L2[v] + T(kChi3) * L3[v]);
-    if (gv[v]) a.L_out[off[v]] = Ln;
+    if (gv[v]) sto(Loq, off[v], Ln);
   }
 
-  // inflow condition with Fresnel reflection and the beams at t_{n+1}
+  // inflow condition with Fresnel reflection and the beams at t_{n+1}.  The
+  // boundary tables (reflection rules, beam factors, detector weights) of the
+  // lane's 4 slots are all requested at once: one memory round trip.
   const bool wave_bnd = __ballot(t.bnd) != 0;
+  const int wl0 = !t.bnd ? -1 : ((t.i == 0) ? 0 : ((t.i == G.nx - 1) ? 1 : -1));
+  const int wl1 = !t.bnd ? -1 : ((t.j == 0) ? 2 : ((t.j == G.ny - 1) ? 3 : -1));
+  double pw0 = 0.0, pw1 = 0.0;
   if (wave_bnd) {
     const int ty = t.bnd ? node_type(t.j, t.i, G.nx, G.ny) : 0;
     const int bp = t.bnd ? boundary_pos(t.j, t.i, G.nx, G.ny) : 0;
+    BcRule br[4];
+    T src[4];
+    double k0[4], k1[4];
+    const int b0 = a.beam_off[q], b1 = a.beam_off[q + 1];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int s = 4 * (4 * t.rt + v) + t.r;
-      BcRule br;
-      br.flag = 0; br.src_a = s; br.src_b = s; br.pad = 0; br.coef_a = 0.0; br.coef_b = 0.0;
-      if (t.bnd && gv[v]) br = a.bc[ty * G.M + s];
-      const T ta = __shfl(un[v], t.node + 16 * (br.src_a & 3));
-      const T tb = __shfl(un[v], t.node + 16 * (br.src_b & 3));
-      if (br.flag) {
-        T val = T(br.coef_a) * ta + T(br.coef_b) * tb;
-        for (int b = a.beam_off[q]; b < a.beam_off[q + 1]; ++b)
-          val += T(a.beam_sp[(int64_t)b * G.nb + bp] * a.beam_an[b * G.M + s]) * T(a.beam_tt[(int64_t)b * G.K1 + a.step + 1]);
-        un[v] = val;
-      }
+      const bool on = t.bnd && gv[v];
+      br[v].flag = 0; br[v].src_a = s; br[v].src_b = s; br[v].pad = 0; br[v].coef_a = 0.0; br[v].coef_b = 0.0;
+      if (on) br[v] = a.bc[ty * G.M + s];
+      src[v] = T(0);
+      if (on)
+        for (int b = b0; b < b1; ++b)
+          src[v] += T(a.beam_sp[(int64_t)b * G.nb + bp] * a.beam_an[b * G.M + s]) * T(a.beam_tt[(int64_t)b * G.K1 + a.step + 1]);
+      k0[v] = (on && a.flux && wl0 >= 0) ? a.kappa[wl0 * G.M + s] : 0.0;
+      k1[v] = (on && a.flux && wl1 >= 0) ? a.kappa[wl1 * G.M + s] : 0.0;
     }
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-    if (gv[v]) a.u_out[off[v]] = un[v];
-  if (a.flux == nullptr) return;
-
-  // detector flux on boundary nodes (FP64): lane partial over its 4 groups,
-  // then over the 4 slot lanes of the node, then over the row tiles
-  double pw0 = 0.0, pw1 = 0.0;
-  const int wl0 = !t.bnd ? -1 : ((t.i == 0) ? 0 : ((t.i == G.nx - 1) ? 1 : -1));
-  const int wl1 = !t.bnd ? -1 : ((t.j == 0) ? 2 : ((t.j == G.ny - 1) ? 3 : -1));
-  if (wave_bnd) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int s = 4 * (4 * t.rt + v) + t.r;
-      if (gv[v] && wl0 >= 0) pw0 += a.kappa[wl0 * G.M + s] * (double)un[v];
-      if (gv[v] && wl1 >= 0) pw1 += a.kappa[wl1 * G.M + s] * (double)un[v];
+      const T ta = __shfl(un[v], t.node + 16 * (br[v].src_a & 3));
+      const T tb = __shfl(un[v], t.node + 16 * (br[v].src_b & 3));
+      if (br[v].flag) un[v] = T(br[v].coef_a) * ta + T(br[v].coef_b) * tb + src[v];
+    }
+    // detector flux on boundary nodes (FP64): lane partial over its 4
+    // groups, then over the 4 slot lanes of the node, then over the row tiles
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      pw0 += k0[v] * (double)un[v];
+      pw1 += k1[v] * (double)un[v];
     }
     pw0 += __shfl_xor(pw0, 16);
     pw1 += __shfl_xor(pw1, 16);
     pw0 += __shfl_xor(pw0, 32);
     pw1 += __shfl_xor(pw1, 32);
   }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (gv[v]) sto(uoq, off[v], un[v]);
+  if (a.flux == nullptr) return;
+
   if (G.RT > 1) {
     if (t.r == 0) {
       Fx[((t.nt * G.RT + t.rt) * 16 + t.node) * 2 + 0] = pw0;
@@ -279,19 +311,28 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
   const int64_t ib = (int64_t)q * G.inst_stride;
   const int Nn = G.nx * G.ny;
 
+  const T* txq = a.atx + ib;
+  const T* tyq = a.aty + ib;
+  T* p1q = a.ap1 + ib;
+  const T* v2q = a.v2 + ib;
+  const T* v3q = a.v3 + ib;
+  const T* v4q = a.v4 + ib;
+  const T* uq = a.u + ib;
+  T* wq = a.w_out + ib;
+  T* v1q = a.v1_out + ib;
   T tx[4], ty[4], p1[4], v2[4], v3[4], v4[4], uu[4];
-  int64_t off[4];
+  uint32_t off[4];
   bool gv[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int g = 4 * t.rt + v;
     gv[v] = t.valid && g < G.G;
-    off[v] = ib + (int64_t)g * G.grp_stride + (int64_t)t.P * kGroup + t.r;
+    off[v] = (uint32_t)(((uint32_t)g * (uint32_t)G.grp_stride + (uint32_t)t.P * kGroup + t.r) * sizeof(T));
     tx[v] = ty[v] = p1[v] = v2[v] = v3[v] = v4[v] = uu[v] = T(0);
     if (gv[v]) {
-      tx[v] = a.atx[off[v]]; ty[v] = a.aty[off[v]]; p1[v] = a.ap1[off[v]];
-      v2[v] = a.v2[off[v]]; v3[v] = a.v3[off[v]]; v4[v] = a.v4[off[v]];
-      uu[v] = a.u[off[v]];
+      tx[v] = ldo(txq, off[v]); ty[v] = ldo(tyq, off[v]); p1[v] = ldo(p1q, off[v]);
+      v2[v] = ldo(v2q, off[v]); v3[v] = ldo(v3q, off[v]); v4[v] = ldo(v4q, off[v]);
+      uu[v] = ldo(uq, off[v]);
     }
   }
   const int gn = t.j * G.nx + t.i;
@@ -304,21 +345,42 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
   T v1[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) v1[v] = T((double)p1[v] - cdt * ((double)tx[v] + (double)ty[v]));
+  // boundary tables of the lane's 4 slots (transposed rules, detector
+  // injection) requested at once
   const bool wave_bnd = __ballot(t.bnd) != 0;
+  T injv[4] = {T(0), T(0), T(0), T(0)};
   if (wave_bnd) {
     const int tyn = t.bnd ? node_type(t.j, t.i, G.nx, G.ny) : 0;
+    const int64_t ib4 = ((int64_t)q * G.K1 + a.step) * 4;
+    const double g0 = (t.bnd && t.i == 0) ? a.inj[(ib4 + 0) * G.npos + t.j] : 0.0;
+    const double g1 = (t.bnd && t.i == G.nx - 1) ? a.inj[(ib4 + 1) * G.npos + t.j] : 0.0;
+    const double g2 = (t.bnd && t.j == 0) ? a.inj[(ib4 + 2) * G.npos + t.i] : 0.0;
+    const double g3 = (t.bnd && t.j == G.ny - 1) ? a.inj[(ib4 + 3) * G.npos + t.i] : 0.0;
+    BcRuleT rt[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int s = 4 * (4 * t.rt + v) + t.r;
-      BcRuleT rt;
-      rt.is_target = 0; rt.ntgt = 0; rt.tgt[0] = s; rt.tgt[1] = s; rt.coef[0] = 0.0; rt.coef[1] = 0.0;
-      if (t.bnd && gv[v]) rt = a.bct[tyn * G.M + s];
-      const T t0 = __shfl(v1[v], t.node + 16 * (rt.tgt[0] & 3));
-      const T t1 = __shfl(v1[v], t.node + 16 * (rt.tgt[1] & 3));
+      const bool on = t.bnd && gv[v];
+      rt[v].is_target = 0; rt[v].ntgt = 0; rt[v].tgt[0] = s; rt[v].tgt[1] = s; rt[v].coef[0] = 0.0; rt[v].coef[1] = 0.0;
+      if (on) rt[v] = a.bct[tyn * G.M + s];
+      // detector misfit enters through the outgoing boundary entries
+      if (on) {
+        T p = T(0);
+        if (t.i == 0) p += T(a.kappa[0 * G.M + s] * g0);
+        if (t.i == G.nx - 1) p += T(a.kappa[1 * G.M + s] * g1);
+        if (t.j == 0) p += T(a.kappa[2 * G.M + s] * g2);
+        if (t.j == G.ny - 1) p += T(a.kappa[3 * G.M + s] * g3);
+        injv[v] = p;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const T t0 = __shfl(v1[v], t.node + 16 * (rt[v].tgt[0] & 3));
+      const T t1 = __shfl(v1[v], t.node + 16 * (rt[v].tgt[1] & 3));
       if (t.bnd && gv[v]) {
-        T val = rt.is_target ? T(0) : v1[v];
-        if (rt.ntgt > 0) val += T(rt.coef[0]) * t0;
-        if (rt.ntgt > 1) val += T(rt.coef[1]) * t1;
+        T val = rt[v].is_target ? T(0) : v1[v];
+        if (rt[v].ntgt > 0) val += T(rt[v].coef[0]) * t0;
+        if (rt[v].ntgt > 1) val += T(rt[v].coef[1]) * t1;
         v1[v] = val;
       }
     }
@@ -337,22 +399,13 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
   // P1^n, stores and the gradient products
   const T cdtT = T(cdt);
   double pa = 0.0, pb = 0.0;
-  const int64_t ib4 = ((int64_t)q * G.K1 + a.step) * 4;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int s = 4 * (4 * t.rt + v) + t.r;
-    T p = v1[v] + cdtT * (B * S[v] - (A + B) * w[v]);
-    if (t.bnd && gv[v]) {
-      // detector misfit enters through the outgoing boundary entries
-      if (t.i == 0) p += T(a.kappa[0 * G.M + s] * a.inj[(ib4 + 0) * G.npos + t.j]);
-      if (t.i == G.nx - 1) p += T(a.kappa[1 * G.M + s] * a.inj[(ib4 + 1) * G.npos + t.j]);
-      if (t.j == 0) p += T(a.kappa[2 * G.M + s] * a.inj[(ib4 + 2) * G.npos + t.i]);
-      if (t.j == G.ny - 1) p += T(a.kappa[3 * G.M + s] * a.inj[(ib4 + 3) * G.npos + t.i]);
-    }
+    const T p = v1[v] + cdtT * (B * S[v] - (A + B) * w[v]) + injv[v];
     if (gv[v]) {
-      a.ap1[off[v]] = p;
-      a.w_out[off[v]] = w[v];
-      a.v1_out[off[v]] = v1[v];
+      sto(p1q, off[v], p);
+      sto(wq, off[v], w[v]);
+      sto(v1q, off[v], v1[v]);
     }
     pa += (double)uu[v] * (double)w[v];
     pb += (double)uu[v] * ((double)S[v] - (double)w[v]);
@@ -389,6 +442,8 @@ static NodeGeom make_geom(const Plan& p) {
   g.RT = (int)(p.Mpad / 16);
   g.NT = p.sched.node_tiles_per_block;
   g.npos_total = (int)(p.ny * p.nxp);
+  g.ntiles = (g.npos_total + 15) / 16;
+  g.tile_shift = (int)((p.ny - 1) * p.nxp / 16);
   g.grp_stride = p.grp_stride;
   g.inst_stride = p.inst_stride;
   return g;

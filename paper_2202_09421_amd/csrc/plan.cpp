@@ -254,6 +254,11 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
   }
   p.grp_stride = p.ny * p.nxp * kGroup;
   p.inst_stride = p.G * p.grp_stride;
+  if (p.inst_stride * (prob->dtype == RTE_F64 ? 8 : 4) >= (int64_t(1) << 32)) {
+    set_error("one source's state exceeds 4 GiB (ordinates x nodes too large)");
+    delete P;
+    return RTE_EUNSUPPORTED;
+  }
   p.K = prob->K;
   p.Nd = n_det;
   p.nbeams = n_beams;
