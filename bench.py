@@ -108,6 +108,77 @@ def cpu_baseline(spec, target_s=15.0):
                       "forward + adjoint gradient, NumPy FP64, 1 thread, %.1f s" % (Ks, spec.K, dt)}
 
 
+def mss_comparison(K, dtype_name, log_fn):
+    """Multiple-staggered-source workload (8 combinations of 2 delayed beams on
+    a 513 x 513 grid, 64 ordinates): the gradient of all combinations in one
+    batched plan (every launch covers all 8) against 8 single-combination plans
+    solved one after another ("plain"), same kernels, graph replay for both.
+    Returns throughputs and the difference of the summed gradients."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2202_09421_amd import rte
+
+    tdt = torch.float64 if dtype_name == "f64" else torch.float32
+    full = W.config(2)
+    spec = full.with_(K=K)
+    ny, nx = spec.Ny + 1, spec.Nx + 1
+    units = nx * ny * spec.M * K
+    res = {}
+
+    def timed_gradient(plan, a, b, gm, reps=2):
+        plan.autotune(a, b, cache=False)
+        plan.set_graph(True)
+        out = plan.gradient(a, b, gm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = plan.gradient(a, b, gm)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, [x.clone() for x in out]
+
+    # batched: one plan, all combinations
+    plan = rte.Plan(spec, tdt)
+    a = torch.tensor(spec.mu_a, device="cuda", dtype=tdt)
+    b = torch.tensor(spec.mu_s, device="cuda", dtype=tdt)
+    gm = torch.zeros((plan.Nq, plan.Nd, K), device="cuda", dtype=torch.float64)
+    tb, (Jb, gab, gbb, Gb) = timed_gradient(plan, a, b, gm)
+    nq = plan.Nq
+    res["batched"] = units * nq / tb
+    log_fn("bench: MSS batched %d combinations, %d steps: %.1f ms" % (nq, K, 1000 * tb))
+    plan.close()
+    del plan
+    torch.cuda.empty_cache()
+
+    # plain: one plan per combination, solved one after another
+    tp, ga_sum, gb_sum = 0.0, None, None
+    for qc in range(nq):
+        beams = [dataclasses.replace(bm, group=0) for bm in spec.beams if bm.group == qc]
+        sq = spec.with_(beams=beams)
+        pq = rte.Plan(sq, tdt)
+        gq = torch.zeros((1, pq.Nd, K), device="cuda", dtype=torch.float64)
+        t, (_, ga, gbq, _) = timed_gradient(pq, a, b, gq)
+        tp += t
+        ga_sum = ga if ga_sum is None else ga_sum + ga
+        gb_sum = gbq if gb_sum is None else gb_sum + gbq
+        pq.close()
+        del pq
+        torch.cuda.empty_cache()
+    res["plain"] = units * nq / tp
+    log_fn("bench: MSS plain %d single-combination solves: %.1f ms" % (nq, 1000 * tp))
+    rel = lambda x, y: float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y))
+    return {"workload": full.name, "grid": "%dx%d" % (nx, ny), "ordinates": spec.M, "combinations": nq,
+            "time_steps": K, "time_steps_full": full.K, "dtype": dtype_name,
+            "sample": "first %d of %d steps, every state kept (the full run needs checkpoints and %s)" % (
+                K, full.K, "two-level storage in FP64" if dtype_name == "f64" else "one-level checkpoints"),
+            "batched_value": res["batched"], "plain_value": res["plain"],
+            "unit": "cell*ordinate*steps/s", "batched_over_plain": res["batched"] / res["plain"],
+            "plain_vs_batched_gradient_rel_diff": max(rel(ga_sum, gab), rel(gb_sum, gbb))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +187,8 @@ def main():
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--mss-steps", type=int, default=150,
+                    help="time steps of the batched-vs-plain MSS comparison (0 skips it)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one eager gradient only (no graph, no events): the command profiled for counters")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -242,6 +315,10 @@ def main():
                           "frac": path_gbs / HBM_PEAK_GBS},
         "kernels": kernels,
     }
+    if args.mss_steps > 0:
+        del plan
+        torch.cuda.empty_cache()
+        out["mss_batched_vs_plain"] = mss_comparison(args.mss_steps, args.dtype, log)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)

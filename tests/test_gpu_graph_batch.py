@@ -98,3 +98,33 @@ def test_graph_gradient_workload_equals_eager(rte):
         J, ga, gb, G = plan.gradient(a, b, gm)
         torch.cuda.synchronize()
         assert torch.equal(J, J0) and torch.equal(ga, ga0) and torch.equal(gb, gb0) and torch.equal(G, G0), rep
+
+
+def test_batched_mss_equals_plain_solves(rte):
+    # three combinations of staggered beams in one plan ("batched") against
+    # one plan per combination ("plain"): the per-combination arithmetic is
+    # the same, and the gradient maps are summed over the combinations in the
+    # same order, so G and the gradients agree bit for bit
+    import dataclasses
+    L = 1.0
+    beams = [W.beam_at(0.5 * L, 0.0, 0, L, 0, L, sigma_t=2.0, t0=6.0, sigma_x=0.2, group=0),
+             W.beam_at(0.5 * L, L, 0, L, 0, L, sigma_t=2.0, t0=6.0, sigma_x=0.2, group=0, tau=3.0),
+             W.beam_at(0.0, 0.4 * L, 0, L, 0, L, sigma_t=2.0, t0=6.0, sigma_x=0.2, group=1, tau=1.0),
+             W.beam_at(L, 0.7 * L, 0, L, 0, L, sigma_t=2.0, t0=6.0, sigma_x=0.2, group=2, tau=2.0)]
+    spec = W.small_problem(N=24, M=16, K=40, seed=31, n_in=1.4, beams=beams)
+    plan = rte.Plan(spec, torch.float64)
+    assert plan.Nq == 3
+    gm = torch.tensor(1e-3 * np.random.default_rng(3).standard_normal((3, plan.Nd, spec.K)), device="cuda")
+    J, ga, gb, G = [x.cpu().numpy().copy() for x in plan.gradient(spec.mu_a, spec.mu_s, gm)]
+    ga_sum = gb_sum = None
+    Js = 0.0
+    for q in range(3):
+        sq = spec.with_(beams=[dataclasses.replace(b, group=0) for b in spec.beams if b.group == q])
+        pq = rte.Plan(sq, torch.float64)
+        Jq, gaq, gbq, Gq = [x.cpu().numpy().copy() for x in pq.gradient(spec.mu_a, spec.mu_s, gm[q:q + 1])]
+        assert np.array_equal(Gq[0], G[q]), q
+        ga_sum = gaq if ga_sum is None else ga_sum + gaq
+        gb_sum = gbq if gb_sum is None else gb_sum + gbq
+        Js += float(Jq[0])
+    assert np.array_equal(ga_sum, ga) and np.array_equal(gb_sum, gb)
+    assert abs(Js - float(J[0])) <= 1e-13 * abs(Js)
