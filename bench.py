@@ -187,6 +187,10 @@ def main():
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--schedule", default=None, metavar="JSON",
+                    help='fixed launch schedule instead of autotuning, e.g. \'{"line_units_per_wave": 1, "line_waves_per_unit": 2}\'')
+    ap.add_argument("--tune-cache", default=None, metavar="JSON",
+                    help="autotuner cache file (reuse one tuned schedule across runs, e.g. profiler passes)")
     ap.add_argument("--mss-steps", type=int, default=150,
                     help="time steps of the batched-vs-plain MSS comparison (0 skips it)")
     ap.add_argument("--profile-run", action="store_true",
@@ -224,7 +228,11 @@ def main():
     a_bg = torch.full((ny, nx), 0.2, device="cuda", dtype=tdt)
     b_bg = torch.full((ny, nx), 50.0, device="cuda", dtype=tdt)
     log("bench: %s, workspace %.1f GB" % (spec.name, plan.workspace_bytes(True) / 1e9))
-    sched = plan.autotune(a_bg, b_bg, cache=False)
+    if args.schedule:
+        plan.set_schedule(json.loads(args.schedule))
+        sched = dict(plan.schedule(), cached=None)
+    else:
+        sched = plan.autotune(a_bg, b_bg, cache=args.tune_cache if args.tune_cache else False)
     log("bench: autotuned schedule %s" % sched)
     G_true = plan.forward(a_true, b_true)
     noise = torch.tensor(W.measured_noise(1, tuple(G_true.shape)), device="cuda")
@@ -237,19 +245,12 @@ def main():
         log("bench: profile run done")
         return
 
-    # (1) per-kernel timing: eager launches bracketed by HIP events on the
-    #     library's stream (the roofline figures below)
+    # (1) one eager gradient (kernels launched one by one)
+    t0 = time.perf_counter()
     plan.gradient(a_bg, b_bg, Gm)
     torch.cuda.synchronize()
-    rte.profile_enable(plan, True)
-    t0 = time.perf_counter()
-    for k in range(max(1, min(2, args.steps))):
-        plan.gradient(a_bg, b_bg, Gm)
-    torch.cuda.synchronize()
-    eager_s = (time.perf_counter() - t0) / max(1, min(2, args.steps))
-    prof = rte.profile_read(plan)
-    rte.profile_enable(plan, False)
-    log("bench: eager gradient with kernel events %.1f ms" % (1000 * eager_s))
+    eager_s = time.perf_counter() - t0
+    log("bench: eager gradient %.1f ms" % (1000 * eager_s))
 
     # (2) the measured steps: the whole gradient recorded once as a HIP graph
     plan.set_graph(True)
@@ -266,6 +267,15 @@ def main():
     log("bench: timed %d gradients in %.3f s (J = %.6e)" % (args.steps, elapsed, float(J.item())))
     if not np.isfinite(float(J.item())) or not torch.isfinite(ga).all():
         raise RuntimeError("non-finite gradient")
+
+    # (3) per-kernel durations (roofline figures), right after the timed
+    #     steps on the same stream: for each kernel class, 20 back-to-back
+    #     launches on the benchmark's shapes recorded as one graph and timed
+    #     between HIP events (rte_plan_time_kernels)
+    reps = 20
+    kus = plan.time_kernels(a_bg, b_bg, reps=reps)
+    log("bench: per-launch kernel times (us) %s" % {k: round(v, 2) for k, v in kus.items()})
+    prof = {k: (v * reps / 1000.0, reps) for k, v in kus.items()}
 
     units_per_grad = nx * ny * spec.M * spec.K * spec.Nq
     ms_per_step = 1000.0 * elapsed / args.steps
@@ -310,7 +320,7 @@ def main():
                      "traffic_over_algorithmic": None if traffic is None else round(traffic["bytes"] / bytes_per_launch, 3),
                      "kernel": dom,
                      "bytes_per_launch": bytes_per_launch,
-                     "timing": "HIP events around each launch, eager launches of the same gradient"},
+                     "timing": "HIP events around a graph of 20 back-to-back launches per kernel class, after the timed steps"},
         "path_roofline": {"algorithmic_bytes_per_unit": PATH_WORDS_STORE_ALL * word, "achieved_GB_s": path_gbs,
                           "frac": path_gbs / HBM_PEAK_GBS},
         "kernels": kernels,

@@ -223,6 +223,17 @@ int rte_profile_enable(rte_plan* plan, int enable);
  * the records.  total_ms and launches point to RTE_K_COUNT entries (host). */
 int rte_profile_read(rte_plan* plan, double* total_ms, int64_t* launches);
 
+/* Per-launch duration (microseconds) of each per-step kernel class with the
+ * plan's current schedule: `reps` (1..10000) back-to-back launches of the
+ * class on the plan's shapes are recorded as one HIP graph, replayed on
+ * `stream` between two HIP events, and the time is divided by `reps`.  The
+ * launches work on zeroed state arrays of `workspace` (>= rte_workspace_bytes
+ * (plan, 1)), which this call overwrites (a saved forward is invalidated).
+ * us points to RTE_K_COUNT doubles (host).  Synchronizes the stream; not for
+ * use under stream capture.                                              */
+int rte_plan_time_kernels(rte_plan* plan, const void* mu_a, const void* mu_s, void* workspace,
+                          int64_t workspace_bytes, void* stream, int reps, double* us);
+
 /* Thread-local message of the last failed call ("" if none). */
 const char* rte_last_error(void);
 

@@ -249,28 +249,35 @@ bool sched_ok(const Plan& p, const rte_schedule& s) {
          node_tiles_ok(p, s.node_tiles_per_block) && (s.line_waves_per_unit == 1 || s.line_waves_per_unit == 2);
 }
 
-// Mean milliseconds per call of `launch` over `reps` calls after one warm-up.
-template <typename F>
-int time_launches(hipStream_t st, int reps, F&& launch, float* ms) {
-  hipEvent_t e0, e1;
-  RTE_CHECK(hipEventCreate(&e0));
-  RTE_CHECK(hipEventCreate(&e1));
-  hipError_t err = launch();
-  if (err == hipSuccess) err = hipEventRecord(e0, st);
-  for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
-  if (err == hipSuccess) err = hipEventRecord(e1, st);
-  if (err == hipSuccess) err = hipEventSynchronize(e1);
-  float t = 0.0f;
-  if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  RTE_CHECK(err);
-  *ms = t / reps;
-  return RTE_OK;
-}
-
-int autotune(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t wsb, hipStream_t st, rte_schedule* out) {
+// Zeroed state-sized arrays of the gradient workspace and the launch records
+// of the four per-step kernel classes on them (timing only: the values do not
+// matter, every access stays inside the workspace).
+struct TuneSet {
   Workspace ws;
+  LineLaunch lf, lb;
+  NodeFwdLaunch nf;
+  NodeAdjLaunch na;
+  int64_t S = 0;   // bytes per state
+  int nst = 2;     // zeroed states at the start of the state store
+  void* state(int k) const { return static_cast<char*>(ws.states) + (int64_t)(k % nst) * S; }
+  // launch r of a timed run reads and writes distinct stored states, as the
+  // time loop does: the forward walks up the store, the adjoint down
+  NodeFwdLaunch fwd_at(int r) const {
+    NodeFwdLaunch L = nf;
+    L.u = state(r);
+    L.u_out = state(r + 1);
+    return L;
+  }
+  NodeAdjLaunch adj_at(int r) const {
+    NodeAdjLaunch L = na;
+    L.u = state(nst - 1 - r % nst);
+    return L;
+  }
+};
+
+int tune_setup(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t wsb, hipStream_t st, int nstates,
+               TuneSet* t) {
+  Workspace& ws = t->ws;
   if (!map_workspace(p, wsp, wsb, true, &ws)) {
     std::ostringstream o;
     o << "workspace too small: need " << workspace_bytes(p, true) << " bytes";
@@ -278,18 +285,92 @@ int autotune(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t wsb
     return RTE_ENOMEM;
   }
   p.have_forward = false;
-  const bool prof = p.prof;
-  p.prof = false;
   const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
   const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  const int64_t cap = p.ckpt_every > 0 ? p.ckpt_every + 1 : p.K + 1;
+  t->S = S;
+  t->nst = (int)std::max<int64_t>(2, std::min<int64_t>(nstates, cap));
+  for (int k = 0; k < t->nst; ++k) RTE_CHECK(launch_zero(static_cast<char*>(ws.states) + k * S, S, st));
   void* u0 = ws.states;
   void* u1 = static_cast<char*>(ws.states) + S;
-  void* arrays[] = {u0, u1, ws.lring[0], ws.lring[1], ws.lring[2], ws.tx, ws.ty, ws.vring[0], ws.vring[1],
+  void* arrays[] = {ws.lring[0], ws.lring[1], ws.lring[2], ws.tx, ws.ty, ws.vring[0], ws.vring[1],
                     ws.vring[2], ws.vring[3], ws.atx, ws.aty, ws.ap1};
   for (void* a : arrays) RTE_CHECK(launch_zero(a, S, st));
   RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
   RTE_CHECK(launch_zero(ws.ga, p.Nq * p.nx * p.ny * 8, st));
   RTE_CHECK(launch_zero(ws.gb, p.Nq * p.nx * p.ny * 8, st));
+  t->lf = LineLaunch{u0, ws.tx, ws.ty, LINE_FWD, 3};
+  t->lb = LineLaunch{ws.wbuf, ws.atx, ws.aty, LINE_ADJ, 3};
+  t->nf = NodeFwdLaunch{u0, ws.tx, ws.ty, ws.lring[1], ws.lring[2], ws.lring[0], mu_a, mu_s, u1, ws.lring[0], ws.flux, 0};
+  t->na = NodeAdjLaunch{ws.atx, ws.aty, ws.ap1, ws.vring[1], ws.vring[2], ws.vring[3], ws.vring[0], u0,
+                        mu_a, mu_s, ws.flux, ws.wbuf, ws.ga, ws.gb, (int)p.K};
+  return RTE_OK;
+}
+
+// Mean microseconds per launch of `launch` over `reps` back-to-back launches
+// recorded as one graph and replayed between two events on st.
+template <typename F>
+int time_graph(Plan& p, hipStream_t st, int reps, F&& launch, double* us) {
+  if (!p.cap_stream) RTE_CHECK(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
+  RTE_CHECK(launch(st, 0));  // warm-up, eager
+  RTE_CHECK(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t err = hipSuccess;
+  for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch(p.cap_stream, r);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(p.cap_stream, &graph);
+  if (err != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    RTE_CHECK(err);
+  }
+  RTE_CHECK(ec);
+  hipGraphExec_t gx = nullptr;
+  err = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  RTE_CHECK(err);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  if (err == hipSuccess) err = hipGraphLaunch(gx, st);  // warm-up replay
+  if (err == hipSuccess) err = hipEventRecord(e0, st);
+  if (err == hipSuccess) err = hipGraphLaunch(gx, st);
+  if (err == hipSuccess) err = hipEventRecord(e1, st);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(gx);
+  RTE_CHECK(err);
+  *us = 1000.0 * ms / reps;
+  return RTE_OK;
+}
+
+int time_kernels(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t wsb, hipStream_t st, int reps,
+                 double* us) {
+  TuneSet t;
+  int rc = tune_setup(p, mu_a, mu_s, wsp, wsb, st, reps + 1, &t);
+  if (rc != RTE_OK) return rc;
+  const bool prof = p.prof;
+  p.prof = false;
+  rc = time_graph(p, st, reps, [&](hipStream_t s, int) { return launch_lines(p, t.lf, s); }, &us[RTE_K_LINES_FWD]);
+  if (rc == RTE_OK)
+    rc = time_graph(p, st, reps, [&](hipStream_t s, int r) { return launch_node_fwd(p, t.fwd_at(r), s); },
+                    &us[RTE_K_NODE_FWD]);
+  if (rc == RTE_OK)
+    rc = time_graph(p, st, reps, [&](hipStream_t s, int r) { return launch_node_adj(p, t.adj_at(r), s); },
+                    &us[RTE_K_NODE_ADJ]);
+  if (rc == RTE_OK)
+    rc = time_graph(p, st, reps, [&](hipStream_t s, int) { return launch_lines(p, t.lb, s); }, &us[RTE_K_LINES_ADJ]);
+  p.prof = prof;
+  return rc;
+}
+
+int autotune(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t wsb, hipStream_t st, rte_schedule* out) {
+  TuneSet tset;
+  int rc0 = tune_setup(p, mu_a, mu_s, wsp, wsb, st, 8, &tset);
+  if (rc0 != RTE_OK) return rc0;
+  const bool prof = p.prof;
+  p.prof = false;
   const int reps = 5;
   const rte_schedule start = p.sched;
   rte_schedule best = p.sched;
@@ -304,16 +385,15 @@ int autotune(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t wsb
     for (int upw : {2, 1})
       for (int nw : {1, 2}) line_cands.push_back({upw, nw, 0});
   line_cands.push_back({1, 1, 1});
-  float best_ms = 1e30f;
+  double best_ms = 1e30;
   for (const auto& c : line_cands) {
     p.sched.line_units_per_wave = c.upw;
     p.sched.line_waves_per_unit = c.nw;
     p.sched.line_generic = c.generic;
-    float f = 0.0f, b = 0.0f;
-    const LineLaunch lf{u0, ws.tx, ws.ty, LINE_FWD, 3};
-    const LineLaunch lb{ws.wbuf, ws.atx, ws.aty, LINE_ADJ, 3};
-    int rc = time_launches(st, reps, [&] { return launch_lines(p, lf, st); }, &f);
-    if (rc == RTE_OK) rc = time_launches(st, reps, [&] { return launch_lines(p, lb, st); }, &b);
+    double f = 0.0, b = 0.0;
+    const LineLaunch lf = tset.lf, lb = tset.lb;
+    int rc = time_graph(p, st, reps, [&](hipStream_t s, int) { return launch_lines(p, lf, s); }, &f);
+    if (rc == RTE_OK) rc = time_graph(p, st, reps, [&](hipStream_t s, int) { return launch_lines(p, lb, s); }, &b);
     if (rc != RTE_OK) {
       p.sched = start;
       p.prof = prof;
@@ -331,16 +411,14 @@ int autotune(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t wsb
   p.sched.line_generic = best.line_generic;
 
   // node passes: tiles per block
-  best_ms = 1e30f;
+  best_ms = 1e30;
   for (int nt : {1, 2, 4}) {
     if (!node_tiles_ok(p, nt)) continue;
     p.sched.node_tiles_per_block = nt;
-    NodeFwdLaunch nf{u0, ws.tx, ws.ty, ws.lring[1], ws.lring[2], ws.lring[0], mu_a, mu_s, u1, ws.lring[0], ws.flux, 0};
-    NodeAdjLaunch na{ws.atx, ws.aty, ws.ap1, ws.vring[1], ws.vring[2], ws.vring[3], ws.vring[0], u0,
-                     mu_a, mu_s, ws.flux, ws.wbuf, ws.ga, ws.gb, (int)p.K};
-    float f = 0.0f, b = 0.0f;
-    int rc = time_launches(st, reps, [&] { return launch_node_fwd(p, nf, st); }, &f);
-    if (rc == RTE_OK) rc = time_launches(st, reps, [&] { return launch_node_adj(p, na, st); }, &b);
+    double f = 0.0, b = 0.0;
+    int rc = time_graph(p, st, reps, [&](hipStream_t s, int r) { return launch_node_fwd(p, tset.fwd_at(r), s); }, &f);
+    if (rc == RTE_OK)
+      rc = time_graph(p, st, reps, [&](hipStream_t s, int r) { return launch_node_adj(p, tset.adj_at(r), s); }, &b);
     if (rc != RTE_OK) {
       p.sched = start;
       p.prof = prof;
@@ -491,6 +569,25 @@ int rte_plan_set_schedule(rte_plan* h, const rte_schedule* sched) {
   p.sched = s;
   ++p.sched_version;
   return RTE_OK;
+}
+
+int rte_plan_time_kernels(rte_plan* h, const void* mu_a, const void* mu_s, void* workspace, int64_t workspace_bytes,
+                          void* stream, int reps, double* us) {
+  if (!nonnull(h, "plan") || !nonnull(mu_a, "mu_a") || !nonnull(mu_s, "mu_s") || !nonnull(workspace, "workspace") ||
+      !nonnull(us, "us"))
+    return RTE_EINVAL;
+  if (reps < 1 || reps > 10000) {
+    set_error("reps must be in [1, 10000]");
+    return RTE_EINVAL;
+  }
+  try {
+    set_error("");
+    return time_kernels(*reinterpret_cast<Plan*>(h), mu_a, mu_s, workspace, workspace_bytes,
+                        static_cast<hipStream_t>(stream), reps, us);
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RTE_EINVAL;
+  }
 }
 
 int rte_plan_autotune(rte_plan* h, const void* mu_a, const void* mu_s, void* workspace, int64_t workspace_bytes,

@@ -96,11 +96,12 @@ def lib():
         L.rte_plan_get_schedule.argtypes = [vp, sp]
         L.rte_plan_set_schedule.argtypes = [vp, sp]
         L.rte_plan_autotune.argtypes = [vp, vp, vp, vp, i64, vp, sp]
+        L.rte_plan_time_kernels.argtypes = [vp, vp, vp, vp, i64, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.rte_last_error.restype = ctypes.c_char_p
         for f in ("rte_plan_create", "rte_plan_destroy", "rte_plan_info", "rte_workspace_bytes", "rte_forward",
                   "rte_adjoint", "rte_gradient", "rte_profile_enable", "rte_profile_read", "rte_plan_set_graph",
                   "rte_batch_create", "rte_batch_destroy", "rte_batch_gradient", "rte_plan_get_schedule",
-                  "rte_plan_set_schedule", "rte_plan_autotune"):
+                  "rte_plan_set_schedule", "rte_plan_autotune", "rte_plan_time_kernels"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -276,6 +277,16 @@ class Plan:
             except OSError:
                 pass
         return dict(chosen, cached=False)
+
+    def time_kernels(self, mu_a, mu_s, reps=20):
+        """Microseconds per launch of each kernel class (KERNEL_CLASSES) with
+        the current schedule, from graph replays of back-to-back launches
+        (rte_plan_time_kernels).  Overwrites the workspace."""
+        a, b = self._medium(mu_a, mu_s)
+        ws = self.workspace(True)
+        us = (ctypes.c_double * len(KERNEL_CLASSES))()
+        _check(lib().rte_plan_time_kernels(self._h, _ptr(a), _ptr(b), _ptr(ws), ws.numel(), _stream(), int(reps), us))
+        return {k: us[i] for i, k in enumerate(KERNEL_CLASSES)}
 
     def set_graph(self, on=True):
         """Graph mode: rte_gradient is recorded once per argument set and

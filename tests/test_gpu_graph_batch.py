@@ -128,3 +128,4 @@ def test_batched_mss_equals_plain_solves(rte):
         Js += float(Jq[0])
     assert np.array_equal(ga_sum, ga) and np.array_equal(gb_sum, gb)
     assert abs(Js - float(J[0])) <= 1e-13 * abs(Js)
+

@@ -100,3 +100,15 @@ def test_autotune_picks_admissible_schedule(rte, tmp_path):
             assert err < 1e-10, (k, err)
         else:
             assert np.array_equal(x, y), k
+
+
+def test_time_kernels(rte):
+    spec = W.small_problem(N=64, M=32, K=10, seed=26, n_in=1.4)
+    ref, plan = _grad(rte, spec)
+    us = plan.time_kernels(spec.mu_a, spec.mu_s, reps=5)
+    say("kernel times (us)", us)
+    assert set(us) == set(rte.KERNEL_CLASSES) and all(0.0 < v < 1e5 for v in us.values())
+    # the workspace was scratch for the timing: a later gradient is unaffected
+    got, _ = _grad(rte, spec)
+    for x, y in zip(got, ref):
+        assert np.array_equal(x, y)
