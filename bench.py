@@ -47,11 +47,14 @@ TRAFFIC_FILE = {"f64": "profiles/gradient_fp64_257x257_M32_K2000_hbm_traffic.md"
 
 
 def source_hash():
-    """sha256 over the kernel sources (file name, then bytes, sorted by name)."""
+    """sha256 over the kernel sources (.hip and .h files of csrc: file name,
+    then bytes, sorted by name); host-only files do not change the traffic."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2202_09421_amd", "csrc", "*"))):
+    files = glob.glob(os.path.join(ROOT, "paper_2202_09421_amd", "csrc", "*.hip")) + \
+        glob.glob(os.path.join(ROOT, "paper_2202_09421_amd", "csrc", "*.h"))
+    for f in sorted(files, key=os.path.basename):
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
