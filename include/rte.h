@@ -169,11 +169,14 @@ int rte_batch_gradient(rte_batch* batch, const void* const* mu_a, const void* co
  * tiles-per-block choices compute the same result bit for bit; the generic
  * line kernel computes the same operator with another FFT factorisation
  * (equal to rounding).  Zero fields mean the default.  The waves-per-unit
- * choice is bitwise neutral as well.
+ * and table-placement choices are bitwise neutral as well.
  *   line_units_per_wave : 1 or 2 work units (two lines x four slots of one
  *                         ordinate group) per workgroup of the four-step line
  *                         kernel, transformed one after the other
  *   line_waves_per_unit : 1 or 2 waves sharing the transforms of one unit
+ *   line_global_tables  : 1 = the FFT twiddles and derivative multipliers are
+ *                         read from global memory (cached) instead of being
+ *                         staged in LDS (smaller LDS footprint)
  *   line_generic        : 1 = use the generic Stockham line kernel even where
  *                         the extended length has a four-step split
  *   node_tiles_per_block: 16-node tiles per workgroup of the node passes
@@ -184,6 +187,8 @@ typedef struct {
   int32_t line_generic;
   int32_t node_tiles_per_block;
   int32_t line_waves_per_unit;
+  int32_t line_global_tables;
+  int32_t reserved;          /* 0 */
 } rte_schedule;
 
 /* Current schedule of the plan (defaults resolved). */

@@ -246,7 +246,8 @@ int graph_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
 // ---- autotuner
 bool sched_ok(const Plan& p, const rte_schedule& s) {
   return (s.line_units_per_wave == 1 || s.line_units_per_wave == 2) && (s.line_generic == 0 || s.line_generic == 1) &&
-         node_tiles_ok(p, s.node_tiles_per_block) && (s.line_waves_per_unit == 1 || s.line_waves_per_unit == 2);
+         node_tiles_ok(p, s.node_tiles_per_block) && (s.line_waves_per_unit == 1 || s.line_waves_per_unit == 2) &&
+         (s.line_global_tables == 0 || s.line_global_tables == 1) && s.reserved == 0;
 }
 
 // Zeroed state-sized arrays of the gradient workspace and the launch records
@@ -377,19 +378,21 @@ int autotune(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t wsb
 
   // line passes: forward and transpose launches of each admissible variant
   struct LineCand {
-    int upw, nw, generic;
+    int upw, nw, generic, tg;
   };
   std::vector<LineCand> line_cands;
   const bool four = p.fcx.n1 > 0 || p.fcy.n1 > 0;
   if (four)
     for (int upw : {2, 1})
-      for (int nw : {1, 2}) line_cands.push_back({upw, nw, 0});
-  line_cands.push_back({1, 1, 1});
+      for (int nw : {1, 2})
+        for (int tg : {0, 1}) line_cands.push_back({upw, nw, 0, tg});
+  line_cands.push_back({1, 1, 1, 0});
   double best_ms = 1e30;
   for (const auto& c : line_cands) {
     p.sched.line_units_per_wave = c.upw;
     p.sched.line_waves_per_unit = c.nw;
     p.sched.line_generic = c.generic;
+    p.sched.line_global_tables = c.tg;
     double f = 0.0, b = 0.0;
     const LineLaunch lf = tset.lf, lb = tset.lb;
     int rc = time_graph(p, st, reps, [&](hipStream_t s, int) { return launch_lines(p, lf, s); }, &f);
@@ -404,11 +407,13 @@ int autotune(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t wsb
       best.line_units_per_wave = c.upw;
       best.line_waves_per_unit = c.nw;
       best.line_generic = c.generic;
+      best.line_global_tables = c.tg;
     }
   }
   p.sched.line_units_per_wave = best.line_units_per_wave;
   p.sched.line_waves_per_unit = best.line_waves_per_unit;
   p.sched.line_generic = best.line_generic;
+  p.sched.line_global_tables = best.line_global_tables;
 
   // node passes: tiles per block
   best_ms = 1e30;
@@ -561,8 +566,8 @@ int rte_plan_set_schedule(rte_plan* h, const rte_schedule* sched) {
   if (!sched_ok(p, s)) {
     std::ostringstream o;
     o << "schedule out of range: line_units_per_wave " << s.line_units_per_wave << ", line_waves_per_unit "
-      << s.line_waves_per_unit << ", line_generic " << s.line_generic << ", node_tiles_per_block "
-      << s.node_tiles_per_block << " (M = " << p.M << ")";
+      << s.line_waves_per_unit << ", line_generic " << s.line_generic << ", line_global_tables "
+      << s.line_global_tables << ", node_tiles_per_block " << s.node_tiles_per_block << " (M = " << p.M << ")";
     set_error(o.str());
     return RTE_EINVAL;
   }

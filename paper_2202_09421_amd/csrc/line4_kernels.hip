@@ -129,8 +129,10 @@ struct L4Smem {
   static constexpr int ROOTS = 2 * NR;
   static constexpr int MU = N;
   static constexpr int FIXED = BUF + FOLD + ROOTS + MU;
-  // nmx = (C + E) * 2d continuation entries
-  static constexpr size_t bytes(int nmx) { return sizeof(double) * (size_t)(FIXED + nmx); }
+  // nmx = (C + E) * 2d continuation entries; TG: twiddles and multipliers
+  // are read from global memory (L1 / L2) instead of being staged
+  static constexpr int mx_off(bool tg) { return BUF + FOLD + (tg ? 0 : ROOTS + MU); }
+  static constexpr size_t bytes(int nmx, bool tg) { return sizeof(double) * (size_t)(mx_off(tg) + nmx); }
 };
 
 __device__ __forceinline__ int rix(int e) { return e + (e >> 4); }
@@ -174,10 +176,12 @@ __device__ __forceinline__ void store_pt(T* out, int64_t ls, int64_t ps, int l, 
 }
 
 // Continuation, derivative (or its transpose) and store of one staged unit.
-template <typename T, bool ADJ, int N1, int N2, int NTH>
+template <typename T, bool ADJ, int N1, int N2, int NTH, bool TG>
 __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int dd, int CE,
                                                int tid, cx<double>* buf, cx<double>* fold, const cx<double>* roots,
                                                const double* mu, const double* Mx) {
+  const double* __restrict__ groots = a.fc.roots;
+  const double* __restrict__ gmu = a.fc.mu;
   typedef L4Smem<N1, N2> SM;
   constexpr int N = SM::N, PS = SM::PS, LSZ = SM::LSZ;
   auto ph = [](int i) { return (i / N2) * PS + i % N2; };
@@ -218,7 +222,8 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
     Dft<N1, -1, double>::run(x);
 #pragma unroll
     for (int k1 = 1; k1 < N1; ++k1) {
-      const cx<double> w = roots[rix((n2 * k1) % N)];
+      const int e = (n2 * k1) % N;
+      const cx<double> w = TG ? cx<double>{groots[2 * e], groots[2 * e + 1]} : roots[rix(e)];
       x[k1] = cx_rot(x[k1], w.re, w.im);
     }
 #pragma unroll
@@ -234,14 +239,15 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
     Dft<N2, -1, double>::run(x);
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
-      const double m = mu[k1 + N1 * k2];
+      const double m = TG ? gmu[k1 + N1 * k2] : mu[k1 + N1 * k2];
       const cx<double> X = x[k2];
       x[k2] = ADJ ? cx<double>{m * X.im, -m * X.re} : cx<double>{-m * X.im, m * X.re};
     }
     Dft<N2, 1, double>::run(x);
 #pragma unroll
     for (int n2 = 1; n2 < N2; ++n2) {
-      const cx<double> w = roots[rix((n2 * k1) % N)];
+      const int e = (n2 * k1) % N;
+      const cx<double> w = TG ? cx<double>{groots[2 * e], groots[2 * e + 1]} : roots[rix(e)];
       x[n2] = cx_rot(x[n2], w.re, -w.im);
     }
 #pragma unroll
@@ -317,22 +323,25 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
 }
 
 // Issue the loads of the FC tables into registers (kept until staged).
-template <int N, int NTH>
+template <int N, int NTH, bool TG>
 struct TabRegs {
-  static constexpr int RT = (N + NTH - 1) / NTH, MT = (N + NTH - 1) / NTH, XT = (kFcTab + NTH - 1) / NTH;
+  static constexpr int RT = TG ? 1 : (N + NTH - 1) / NTH, MT = TG ? 1 : (N + NTH - 1) / NTH,
+                       XT = (kFcTab + NTH - 1) / NTH;
   double rr[RT][2], mm[MT], xx[XT];
   __device__ __forceinline__ void load(const FcPlanDev& fc, int lane) {
     const int nmx = 2 * fc.d * (fc.C + fc.E);
+    if (!TG) {
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int k = lane + NTH * t;
-      rr[t][0] = (k < N) ? fc.roots[2 * k] : 0.0;
-      rr[t][1] = (k < N) ? fc.roots[2 * k + 1] : 0.0;
-    }
+      for (int t = 0; t < RT; ++t) {
+        const int k = lane + NTH * t;
+        rr[t][0] = (k < N) ? fc.roots[2 * k] : 0.0;
+        rr[t][1] = (k < N) ? fc.roots[2 * k + 1] : 0.0;
+      }
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      const int k = lane + NTH * t;
-      mm[t] = (k < N) ? fc.mu[k] : 0.0;
+      for (int t = 0; t < MT; ++t) {
+        const int k = lane + NTH * t;
+        mm[t] = (k < N) ? fc.mu[k] : 0.0;
+      }
     }
 #pragma unroll
     for (int t = 0; t < XT; ++t) {
@@ -341,15 +350,17 @@ struct TabRegs {
     }
   }
   __device__ __forceinline__ void stage(cx<double>* roots, double* mu, double* Mx, int nmx, int lane) const {
+    if (!TG) {
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int k = lane + NTH * t;
-      if (k < N) roots[rix(k)] = {rr[t][0], rr[t][1]};
-    }
+      for (int t = 0; t < RT; ++t) {
+        const int k = lane + NTH * t;
+        if (k < N) roots[rix(k)] = {rr[t][0], rr[t][1]};
+      }
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      const int k = lane + NTH * t;
-      if (k < N) mu[k] = mm[t];
+      for (int t = 0; t < MT; ++t) {
+        const int k = lane + NTH * t;
+        if (k < N) mu[k] = mm[t];
+      }
     }
 #pragma unroll
     for (int t = 0; t < XT; ++t) {
@@ -364,7 +375,7 @@ struct TabRegs {
 // before the first transform.  UPW = 1 (also for long lines, whose loads alone
 // would fill the register file): tables first, then the unit in chunks of
 // 8 load slots per thread.
-template <typename T, bool ADJ, int N1, int N2, int UPW, int NW>
+template <typename T, bool ADJ, int N1, int N2, int UPW, int NW, bool TG>
 __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
   constexpr int N = N1 * N2;
   constexpr int NTH = 64 * NW;
@@ -376,7 +387,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
   cx<double>* fold = reinterpret_cast<cx<double>*>(sm + SM::BUF);
   cx<double>* roots = reinterpret_cast<cx<double>*>(sm + SM::BUF + SM::FOLD);
   double* mu = sm + SM::BUF + SM::FOLD + SM::ROOTS;
-  double* Mx = mu + SM::MU;
+  double* Mx = sm + SM::mx_off(TG);
 
   const FcPlanDev& fc = a.fc;
   const int n = fc.n, dd = fc.d, CE = fc.C + fc.E;
@@ -388,25 +399,25 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
     UnitRegs<T, TMAX> R0, R1;
     load_unit<T, TMAX, NTH>(a, d0, n, tid, R0);
     load_unit<T, TMAX, NTH>(a, d1, n, tid, R1);
-    TabRegs<N, NTH> tab;
+    TabRegs<N, NTH, TG> tab;
     tab.load(fc, tid);
     tab.stage(roots, mu, Mx, 2 * dd * CE, tid);
     if (d0.live) {
       stage_unit<T, TMAX, N1, N2, NTH>(R0, d0, a.coef[d0.dir], ADJ, n, tid, buf);
       __syncthreads();
-      transform_unit<T, ADJ, N1, N2, NTH>(a, d0, n, dd, CE, tid, buf, fold, roots, mu, Mx);
+      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, fold, roots, mu, Mx);
     }
     if (d1.live) {
       __syncthreads();
       stage_unit<T, TMAX, N1, N2, NTH>(R1, d1, a.coef[d1.dir], ADJ, n, tid, buf);
       __syncthreads();
-      transform_unit<T, ADJ, N1, N2, NTH>(a, d1, n, dd, CE, tid, buf, fold, roots, mu, Mx);
+      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d1, n, dd, CE, tid, buf, fold, roots, mu, Mx);
     }
   } else {
     const UnitDesc d0 = decode_unit(a, remap_unit16((int)blockIdx.x));
     if (!d0.live) return;
     {
-      TabRegs<N, NTH> tab;
+      TabRegs<N, NTH, TG> tab;
       tab.load(fc, tid);
       tab.stage(roots, mu, Mx, 2 * dd * CE, tid);
     }
@@ -454,7 +465,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
       }
     }
     __syncthreads();
-    transform_unit<T, ADJ, N1, N2, NTH>(a, d0, n, dd, CE, tid, buf, fold, roots, mu, Mx);
+    transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, fold, roots, mu, Mx);
   }
 }
 
@@ -464,7 +475,6 @@ bool fourstep_split(int Np, int* n1, int* n2) {
     case 160: *n1 = 16; *n2 = 10; return true;
     case 288: *n1 = 16; *n2 = 18; return true;
     case 540: *n1 = 20; *n2 = 27; return true;
-    case 1080: *n1 = 30; *n2 = 36; return true;
     default: return false;
   }
 }
@@ -473,37 +483,37 @@ bool fourstep_split(int Np, int* n1, int* n2) {
 template <int N1, int N2, int NW>
 constexpr bool kPairOk = (2 * N1 * N2 + 64 * NW - 1) / (64 * NW) <= 9;
 
-template <typename T, bool ADJ, int N1, int N2, int NW>
-static hipError_t go_nw(const Lines4Args<T>& a, int upw, size_t sh, hipStream_t s) {
+template <typename T, bool ADJ, int N1, int N2, int NW, bool TG>
+static hipError_t go_nw(const Lines4Args<T>& a, int upw, hipStream_t s) {
+  const size_t sh = L4Smem<N1, N2>::bytes(2 * a.fc.d * (a.fc.C + a.fc.E), TG);
+  if (sh > kLines4MaxLds) return hipErrorNotSupported;
   if constexpr (kPairOk<N1, N2, NW>) {
     if (upw == 2) {
       const int groups = (a.nunits + 1) / 2;
       if (groups == 0) return hipSuccess;
-      hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, 2, NW>), dim3((unsigned)groups), dim3(64 * NW), sh, s, a);
+      hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, 2, NW, TG>), dim3((unsigned)groups), dim3(64 * NW), sh, s, a);
       return hipGetLastError();
     }
   }
   if (a.nunits == 0) return hipSuccess;
   const int groups = ((a.nunits + 15) / 16) * 16;
-  hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, 1, NW>), dim3((unsigned)groups), dim3(64 * NW), sh, s, a);
+  hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, 1, NW, TG>), dim3((unsigned)groups), dim3(64 * NW), sh, s, a);
   return hipGetLastError();
 }
 
 template <typename T, bool ADJ, int N1, int N2>
-static hipError_t go(const Lines4Args<T>& a, int upw, int nw, hipStream_t s) {
-  const size_t sh = L4Smem<N1, N2>::bytes(2 * a.fc.d * (a.fc.C + a.fc.E));
-  if (sh > kLines4MaxLds) return hipErrorNotSupported;
-  return nw == 2 ? go_nw<T, ADJ, N1, N2, 2>(a, upw, sh, s) : go_nw<T, ADJ, N1, N2, 1>(a, upw, sh, s);
+static hipError_t go(const Lines4Args<T>& a, int upw, int nw, int tg, hipStream_t s) {
+  if (tg) return nw == 2 ? go_nw<T, ADJ, N1, N2, 2, true>(a, upw, s) : go_nw<T, ADJ, N1, N2, 1, true>(a, upw, s);
+  return nw == 2 ? go_nw<T, ADJ, N1, N2, 2, false>(a, upw, s) : go_nw<T, ADJ, N1, N2, 1, false>(a, upw, s);
 }
 
 template <typename T, bool ADJ>
-static hipError_t by_size(const Lines4Args<T>& a, int upw, int nw, hipStream_t s) {
+static hipError_t by_size(const Lines4Args<T>& a, int upw, int nw, int tg, hipStream_t s) {
   switch (a.fc.Np) {
-    case 90: return go<T, ADJ, 9, 10>(a, upw, nw, s);
-    case 160: return go<T, ADJ, 16, 10>(a, upw, nw, s);
-    case 288: return go<T, ADJ, 16, 18>(a, upw, nw, s);
-    case 540: return go<T, ADJ, 20, 27>(a, upw, nw, s);
-    case 1080: return go<T, ADJ, 30, 36>(a, upw, nw, s);
+    case 90: return go<T, ADJ, 9, 10>(a, upw, nw, tg, s);
+    case 160: return go<T, ADJ, 16, 10>(a, upw, nw, tg, s);
+    case 288: return go<T, ADJ, 16, 18>(a, upw, nw, tg, s);
+    case 540: return go<T, ADJ, 20, 27>(a, upw, nw, tg, s);
     default: return hipErrorNotSupported;
   }
 }
@@ -535,8 +545,8 @@ static hipError_t launch4_t(const Plan& p, const LineLaunch& L, hipStream_t s) {
   const int64_t per = p.Nq * p.G;
   a.units_first = (int)(per * a.npe[a.dir_first]);
   a.nunits = a.units_first + ((dx && dy) ? (int)(per * a.npe[1]) : 0);
-  const int upw = p.sched.line_units_per_wave, nw = p.sched.line_waves_per_unit;
-  return L.mode == LINE_ADJ ? by_size<T, true>(a, upw, nw, s) : by_size<T, false>(a, upw, nw, s);
+  const int upw = p.sched.line_units_per_wave, nw = p.sched.line_waves_per_unit, tg = p.sched.line_global_tables;
+  return L.mode == LINE_ADJ ? by_size<T, true>(a, upw, nw, tg, s) : by_size<T, false>(a, upw, nw, tg, s);
 }
 
 hipError_t launch_lines4(const Plan& p, const LineLaunch& L, hipStream_t s) {

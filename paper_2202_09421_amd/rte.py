@@ -59,11 +59,13 @@ class rte_detector(ctypes.Structure):
 
 class rte_schedule(ctypes.Structure):
     _fields_ = [("line_units_per_wave", ctypes.c_int32), ("line_generic", ctypes.c_int32),
-                ("node_tiles_per_block", ctypes.c_int32), ("line_waves_per_unit", ctypes.c_int32)]
+                ("node_tiles_per_block", ctypes.c_int32), ("line_waves_per_unit", ctypes.c_int32),
+                ("line_global_tables", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {"line_units_per_wave": self.line_units_per_wave, "line_generic": self.line_generic,
-                "node_tiles_per_block": self.node_tiles_per_block, "line_waves_per_unit": self.line_waves_per_unit}
+                "node_tiles_per_block": self.node_tiles_per_block, "line_waves_per_unit": self.line_waves_per_unit,
+                "line_global_tables": self.line_global_tables}
 
 
 _lib = None
@@ -231,7 +233,8 @@ class Plan:
 
     def set_schedule(self, sched):
         sc = rte_schedule(int(sched.get("line_units_per_wave", 0)), int(sched.get("line_generic", 0)),
-                          int(sched.get("node_tiles_per_block", 0)), int(sched.get("line_waves_per_unit", 0)))
+                          int(sched.get("node_tiles_per_block", 0)), int(sched.get("line_waves_per_unit", 0)),
+                          int(sched.get("line_global_tables", 0)), 0)
         _check(lib().rte_plan_set_schedule(self._h, ctypes.byref(sc)))
 
     def tune_key(self):

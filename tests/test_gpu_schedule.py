@@ -50,7 +50,9 @@ def test_schedules_bitwise_equal(rte, M):
     say("default schedule", plan.schedule())
     for sched in ({"line_units_per_wave": 1}, {"line_units_per_wave": 2, "node_tiles_per_block": 1},
                   {"node_tiles_per_block": 2}, {"node_tiles_per_block": 4}, {"line_waves_per_unit": 2},
-                  {"line_units_per_wave": 1, "line_waves_per_unit": 2}):
+                  {"line_units_per_wave": 1, "line_waves_per_unit": 2},
+                  {"line_units_per_wave": 1, "line_waves_per_unit": 2, "line_global_tables": 1},
+                  {"line_units_per_wave": 2, "line_global_tables": 1}):
         say("schedule", sched)
         got, _ = _grad(rte, spec, sched)
         for k, (x, y) in enumerate(zip(got, ref)):
@@ -71,7 +73,7 @@ def test_schedule_rejects_out_of_range(rte):
     spec = W.small_problem(N=16, M=32, K=4, seed=23)
     plan = rte.Plan(spec, torch.float64)
     for bad in ({"line_units_per_wave": 3}, {"line_generic": 2}, {"node_tiles_per_block": 3},
-                {"node_tiles_per_block": 8}, {"line_waves_per_unit": 4}):
+                {"node_tiles_per_block": 8}, {"line_waves_per_unit": 4}, {"line_global_tables": 2}):
         with pytest.raises(rte.RteError):
             plan.set_schedule(bad)
     big = rte.Plan(W.small_problem(N=12, M=80, K=2, seed=24), torch.float64)
