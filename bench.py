@@ -182,6 +182,62 @@ def mss_comparison(K, dtype_name, log_fn):
             "plain_vs_batched_gradient_rel_diff": max(rel(ga_sum, gab), rel(gb_sum, gbb))}
 
 
+def uneven_comparison(scale, log_fn, count=32):
+    """The uneven batch (independent instances of different grids, ordinate
+    counts and step counts; grids and steps scaled by `scale`): all instances
+    in one graph launch with one branch per instance ("batched") against the
+    instances one after another, each as its own recorded graph ("plain")."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2202_09421_amd import rte
+
+    specs = W.uneven_batch(count=count, scale=scale)
+    plans, media, gms, units = [], [], [], 0
+    for sp in specs:
+        ny, nx = sp.Ny + 1, sp.Nx + 1
+        state = 8 * ny * (((nx + 3) // 4) * 4) * sp.M
+        ck = 0 if (sp.K + 1) * state < 2e9 else max(8, int(math.sqrt(4 * sp.K)))
+        pl = rte.Plan(sp, torch.float64, ckpt_every=ck)
+        plans.append(pl)
+        media.append((torch.tensor(sp.mu_a, device="cuda"), torch.tensor(sp.mu_s, device="cuda")))
+        gms.append(torch.zeros((1, pl.Nd, sp.K), device="cuda", dtype=torch.float64))
+        units += nx * ny * sp.M * sp.K
+    batch = rte.Batch(plans)
+    batch.gradient(media, gms)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.gradient(media, gms)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    log_fn("bench: uneven batch of %d instances, one graph launch: %.1f ms" % (len(plans), 1000 * tb))
+    for pl in plans:
+        pl.set_graph(True)
+    for pl, (a, b), g in zip(plans, media, gms):
+        pl.gradient(a, b, g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pl, (a, b), g in zip(plans, media, gms):
+        pl.gradient(a, b, g)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    log_fn("bench: uneven batch, instances one after another: %.1f ms" % (1000 * tp))
+    batch.close()
+    for pl in plans:
+        pl.close()
+    torch.cuda.empty_cache()
+    return {"workload": "uneven batch of %d instances" % len(specs), "scale": scale,
+            "grids": "%d..%d" % (min(s.Nx + 1 for s in specs), max(s.Nx + 1 for s in specs)),
+            "ordinates": sorted(set(s.M for s in specs)), "steps": "%d..%d" % (min(s.K for s in specs), max(s.K for s in specs)),
+            "dtype": "f64", "units": units, "batched_value": units / tb, "plain_value": units / tp,
+            "unit": "cell*ordinate*steps/s", "batched_over_plain": tp / tb,
+            "note": "grids and step counts scaled by %.2f from the 128..512-node, 500..3000-step batch; "
+                    "instances above 2 GB of states use checkpoints (one forward replay)" % scale}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +250,8 @@ def main():
                     help='fixed launch schedule instead of autotuning, e.g. \'{"line_units_per_wave": 1, "line_waves_per_unit": 2}\'')
     ap.add_argument("--tune-cache", default=None, metavar="JSON",
                     help="autotuner cache file (reuse one tuned schedule across runs, e.g. profiler passes)")
+    ap.add_argument("--uneven-scale", type=float, default=0.5,
+                    help="grid and step scale of the uneven-batch comparison (0 skips it)")
     ap.add_argument("--mss-steps", type=int, default=150,
                     help="time steps of the batched-vs-plain MSS comparison (0 skips it)")
     ap.add_argument("--profile-run", action="store_true",
@@ -328,10 +386,14 @@ def main():
                           "frac": path_gbs / HBM_PEAK_GBS},
         "kernels": kernels,
     }
-    if args.mss_steps > 0:
+    if args.mss_steps > 0 or args.uneven_scale > 0:
+        plan.close()
         del plan
         torch.cuda.empty_cache()
+    if args.mss_steps > 0:
         out["mss_batched_vs_plain"] = mss_comparison(args.mss_steps, args.dtype, log)
+    if args.uneven_scale > 0:
+        out["uneven_batched_vs_plain"] = uneven_comparison(args.uneven_scale, log)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)

@@ -168,8 +168,11 @@ int rte_batch_gradient(rte_batch* batch, const void* const* mu_a, const void* co
 /* Launch schedule of the per-step kernels.  The units-per-wave and
  * tiles-per-block choices compute the same result bit for bit; the generic
  * line kernel computes the same operator with another FFT factorisation
- * (equal to rounding).  Zero fields mean the default.  The waves-per-unit
- * and table-placement choices are bitwise neutral as well.
+ * (equal to rounding).  Zero fields mean the default (one unit per
+ * workgroup, two waves per unit, tables staged unless set, the node tiling
+ * of the plan).  The waves-per-unit and table-placement choices are bitwise
+ * neutral as well.  Extended lengths outside {90, 160, 288, 540} have one
+ * four-step variant (one unit, two waves, global tables) whatever is set.
  *   line_units_per_wave : 1 or 2 work units (two lines x four slots of one
  *                         ordinate group) per workgroup of the four-step line
  *                         kernel, transformed one after the other

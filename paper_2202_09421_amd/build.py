@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librte.so")
-SOURCES = ["plan.cpp", "capi.cpp", "line_kernels.hip", "line4_kernels.hip", "node_kernels.hip"]
+SOURCES = ["plan.cpp", "capi.cpp", "line_kernels.hip", "line4_kernels.hip", "line4_extra0.hip", "line4_extra1.hip",
+           "line4_extra2.hip", "line4_extra3.hip", "node_kernels.hip"]
 ARCH = os.environ.get("RTE_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -43,7 +44,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs

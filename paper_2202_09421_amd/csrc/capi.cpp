@@ -560,8 +560,8 @@ int rte_plan_set_schedule(rte_plan* h, const rte_schedule* sched) {
   if (!nonnull(h, "plan") || !nonnull(sched, "sched")) return RTE_EINVAL;
   Plan& p = *reinterpret_cast<Plan*>(h);
   rte_schedule s = *sched;
-  if (s.line_units_per_wave == 0) s.line_units_per_wave = 2;
-  if (s.line_waves_per_unit == 0) s.line_waves_per_unit = 1;
+  if (s.line_units_per_wave == 0) s.line_units_per_wave = 1;
+  if (s.line_waves_per_unit == 0) s.line_waves_per_unit = 2;
   if (s.node_tiles_per_block == 0) s.node_tiles_per_block = node_tiles_default(p);
   if (!sched_ok(p, s)) {
     std::ostringstream o;

@@ -1,504 +1,65 @@
-// Four-step line passes for the common extended lengths N_p = N1 * N2.
-//
-// FC-Gram continuation + filtered spectral derivative along x lines (rows)
-// and y lines (columns) of one state, or the exact transpose (Sec. 4.3).
-// The DFT of length N_p is split as in the four-step algorithm:
-//   A : N2 transforms of length N1 over the stride-N2 index, twiddle w^{n2 k1}
-//   B : N1 transforms of length N2 over each contiguous block, multiply by
-//       the derivative factor i mu_k at k = k1 + N1 k2, inverse length-N2
-//       transform, twiddle w^{-n2 k1}
-//   A': N2 inverse transforms of length N1
-// Each transform is a compile-time codelet held in registers, so a line makes
-// three LDS round trips.
-//
-// Work unit: two neighbouring lines of one ordinate group (four complex
-// lines: slots r0 + i r1 and r2 + i r3 of each line, differentiated together
-// since the operator is real-linear).  A workgroup is one wave and handles
-// two consecutive units; every global load of both units, and of the FC
-// tables, is issued before the first one is transformed, so the memory
-// latency is paid once per wave.  x units come first, then y units; unit
-// pairs are even-aligned so a wave's two y units cover four adjacent
-// columns, i.e. whole 128-byte segments of the row-aligned state.
-#include "fft_codelets.h"
-#include "rte_internal.h"
+// Four-step line passes: launch code for all extended lengths, full set of
+// tuned variants for N_p in {90, 160, 288, 540}.
+#include "line4_impl.h"
 
 namespace rte {
 
-template <typename T>
-struct Lines4Args {
-  const T* in;
-  T* out[2];
-  const double* coef[2];   // xi, eta in slot order
-  FcPlanDev fc;            // identical for every direction of the launch
-  int nlines[2];
-  int npe[2];              // line pairs per (source, group), rounded up to even
-  int64_t line_stride[2], pt_stride[2];
-  int64_t grp_stride, inst_stride;
-  int G;
-  int dir_first;           // direction of units [0, units_first)
-  int units_first;
-  int nunits;
-};
-
-constexpr int kLP = 4;  // complex lines per unit (two lines x slot pairs)
-
-// One unit per workgroup: workgroup b runs on XCD b % 8, so units 2x and
-// 2x + 1 of each chunk of 16 (the two column pairs of one 128-byte row
-// segment) go to workgroups b and b + 8 of that chunk, i.e. to one XCD and
-// its L2.
-__device__ __forceinline__ int remap_unit16(int b) {
-  const int chunk = b >> 4, x = b & 7, h = (b >> 3) & 1;
-  return chunk * 16 + 2 * x + h;
-}
-constexpr size_t kLines4MaxLds = 64 * 1024;
-
-// thread-owned loads of one unit: point i of line it (0/1) for
-// e = tid + NTH t, i = e / 2, it = e % 2; 4 slots each
-template <typename T, int TMAX>
-struct UnitRegs {
-  T v[TMAX][4];
-};
-
-struct UnitDesc {
-  int dir;
-  bool live, has1;
-  int64_t base;
-  int s0;
-};
-
-template <typename T>
-__device__ __forceinline__ UnitDesc decode_unit(const Lines4Args<T>& a, int u) {
-  UnitDesc d;
-  int r = u;
-  d.dir = a.dir_first;
-  if (u >= a.units_first) {
-    d.dir = 1 - a.dir_first;
-    r = u - a.units_first;
-  }
-  const int npe = a.npe[d.dir];
-  const int pair = r % npe;
-  const int g = (r / npe) % a.G;
-  const int q = r / (npe * a.G);
-  const int line0 = 2 * pair;
-  d.live = (u < a.nunits) && (line0 < a.nlines[d.dir]);
-  d.has1 = line0 + 1 < a.nlines[d.dir];
-  d.base = (int64_t)q * a.inst_stride + (int64_t)g * a.grp_stride + (int64_t)line0 * a.line_stride[d.dir];
-  d.s0 = g * kGroup;
-  return d;
-}
-
-template <typename T, int TMAX, int NTH>
-__device__ __forceinline__ void load_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int tid,
-                                          UnitRegs<T, TMAX>& R) {
-  const T* in = a.in + d.base;
-  const int64_t ls = a.line_stride[d.dir], ps = a.pt_stride[d.dir];
-#pragma unroll
-  for (int t = 0; t < TMAX; ++t) {
-    const int e = tid + NTH * t, it = e & 1, i = e >> 1;
-    if (d.live && i < n && (it == 0 || d.has1)) {
-      const T* p = in + it * ls + (int64_t)i * ps;
-      if constexpr (sizeof(T) == 8) {
-        const double2 x = reinterpret_cast<const double2*>(p)[0];
-        const double2 y = reinterpret_cast<const double2*>(p)[1];
-        R.v[t][0] = x.x; R.v[t][1] = x.y; R.v[t][2] = y.x; R.v[t][3] = y.y;
-      } else {
-        const float4 x = *reinterpret_cast<const float4*>(p);
-        R.v[t][0] = x.x; R.v[t][1] = x.y; R.v[t][2] = x.z; R.v[t][3] = x.w;
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) R.v[t][r] = T(0);
-    }
-  }
-}
-
-// LDS layout (doubles): buf [kLP][LSZ] complex (rows of N2 + 1 entries, line
-// stride LSZ = 2 mod 4 entries so that the two lines stored by neighbouring
-// lanes fall in different bank halves) | fold [kLP][2 kMaxFcD] complex |
-// roots, complex, entry e at e + e / 16 (spreads the strided twiddle reads
-// over the banks) | mu [N] | continuation matrix [(C+E) x 2d]
-template <int N1, int N2>
-struct L4Smem {
-  static constexpr int N = N1 * N2;
-  static constexpr int PS = N2 + 1;
-  static constexpr int LSZ0 = N1 * PS;
-  static constexpr int LSZ = LSZ0 + (6 - LSZ0 % 4) % 4;
-  static constexpr int NR = N + N / 16 + 1;
-  static constexpr int BUF = 2 * kLP * LSZ;
-  static constexpr int FOLD = 2 * kLP * 2 * kMaxFcD;
-  static constexpr int ROOTS = 2 * NR;
-  static constexpr int MU = N;
-  static constexpr int FIXED = BUF + FOLD + ROOTS + MU;
-  // nmx = (C + E) * 2d continuation entries; TG: twiddles and multipliers
-  // are read from global memory (L1 / L2) instead of being staged
-  static constexpr int mx_off(bool tg) { return BUF + FOLD + (tg ? 0 : ROOTS + MU); }
-  static constexpr size_t bytes(int nmx, bool tg) { return sizeof(double) * (size_t)(mx_off(tg) + nmx); }
-};
-
-__device__ __forceinline__ int rix(int e) { return e + (e >> 4); }
-
-template <typename T, int TMAX, int N1, int N2, int NTH>
-__device__ __forceinline__ void stage_unit(const UnitRegs<T, TMAX>& R, const UnitDesc& d, const double* coef,
-                                           bool adj, int n, int tid, cx<double>* buf) {
-  typedef L4Smem<N1, N2> SM;
-  double cf[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) cf[r] = adj ? coef[d.s0 + r] : 1.0;
-#pragma unroll
-  for (int t = 0; t < TMAX; ++t) {
-    const int e = tid + NTH * t, it = e & 1, i = e >> 1;
-    if (i < n) {
-      const int ph = (i / N2) * SM::PS + i % N2;
-      buf[(2 * it) * SM::LSZ + ph] = {cf[0] * (double)R.v[t][0], cf[1] * (double)R.v[t][1]};
-      buf[(2 * it + 1) * SM::LSZ + ph] = {cf[2] * (double)R.v[t][2], cf[3] * (double)R.v[t][3]};
-    }
-  }
-  if (adj) {
-    const int ext = SM::N - n;
-    for (int e = tid; e < kLP * ext; e += NTH) {
-      const int l = e / ext, i = n + e % ext;
-      buf[l * SM::LSZ + (i / N2) * SM::PS + i % N2] = {0.0, 0.0};
-    }
-  }
-}
-
-// Store one complex point of complex line l (line l / 2 of the pair, slots
-// 2 (l % 2) and 2 (l % 2) + 1), scaled by (c0, c1).
-template <typename T>
-__device__ __forceinline__ void store_pt(T* out, int64_t ls, int64_t ps, int l, int p, double re, double im, double c0,
-                                         double c1) {
-  T* q = out + (l >> 1) * ls + (int64_t)p * ps + 2 * (l & 1);
-  if constexpr (sizeof(T) == 8) {
-    *reinterpret_cast<double2*>(q) = make_double2(c0 * re, c1 * im);
-  } else {
-    *reinterpret_cast<float2*>(q) = make_float2(float(c0 * re), float(c1 * im));
-  }
-}
-
-// Continuation, derivative (or its transpose) and store of one staged unit.
-template <typename T, bool ADJ, int N1, int N2, int NTH, bool TG>
-__device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int dd, int CE,
-                                               int tid, cx<double>* buf, cx<double>* fold, const cx<double>* roots,
-                                               const double* mu, const double* Mx) {
-  const double* __restrict__ groots = a.fc.roots;
-  const double* __restrict__ gmu = a.fc.mu;
-  typedef L4Smem<N1, N2> SM;
-  constexpr int N = SM::N, PS = SM::PS, LSZ = SM::LSZ;
-  auto ph = [](int i) { return (i / N2) * PS + i % N2; };
-
-  if (!ADJ) {
-    // extension values (Sec. 4.3 steps 1-4 as one linear map of the 2d
-    // matching values); lane p < C + E computes position n + p of each line
-    if (tid < CE) {
-      const int lane = tid;
-      double sr[kLP], si[kLP];
-#pragma unroll
-      for (int l = 0; l < kLP; ++l) sr[l] = si[l] = 0.0;
-#pragma unroll
-      for (int k = 0; k < kMaxFcD; ++k) {
-        if (k < dd) {
-          const double mr = Mx[lane * 2 * dd + k], ml = Mx[lane * 2 * dd + dd + k];
-#pragma unroll
-          for (int l = 0; l < kLP; ++l) {
-            const cx<double> gr = buf[l * LSZ + ph(n - dd + k)];
-            const cx<double> gl = buf[l * LSZ + ph(dd - 1 - k)];
-            sr[l] += mr * gr.re + ml * gl.re;
-            si[l] += mr * gr.im + ml * gl.im;
-          }
-        }
-      }
-#pragma unroll
-      for (int l = 0; l < kLP; ++l) buf[l * LSZ + ph(n + lane)] = {sr[l], si[l]};
-    }
-    __syncthreads();
-  }
-
-  // step A: length-N1 transforms along the stride-N2 index
-  for (int job = tid; job < kLP * N2; job += NTH) {
-    const int l = job / N2, n2 = job % N2;
-    cx<double> x[N1];
-#pragma unroll
-    for (int i = 0; i < N1; ++i) x[i] = buf[l * LSZ + i * PS + n2];
-    Dft<N1, -1, double>::run(x);
-#pragma unroll
-    for (int k1 = 1; k1 < N1; ++k1) {
-      const int e = (n2 * k1) % N;
-      const cx<double> w = TG ? cx<double>{groots[2 * e], groots[2 * e + 1]} : roots[rix(e)];
-      x[k1] = cx_rot(x[k1], w.re, w.im);
-    }
-#pragma unroll
-    for (int i = 0; i < N1; ++i) buf[l * LSZ + i * PS + n2] = x[i];
-  }
-  __syncthreads();
-  // step B: length-N2 transforms, derivative factor, inverse transforms
-  for (int job = tid; job < kLP * N1; job += NTH) {
-    const int l = job / N1, k1 = job % N1;
-    cx<double> x[N2];
-#pragma unroll
-    for (int i = 0; i < N2; ++i) x[i] = buf[l * LSZ + k1 * PS + i];
-    Dft<N2, -1, double>::run(x);
-#pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) {
-      const double m = TG ? gmu[k1 + N1 * k2] : mu[k1 + N1 * k2];
-      const cx<double> X = x[k2];
-      x[k2] = ADJ ? cx<double>{m * X.im, -m * X.re} : cx<double>{-m * X.im, m * X.re};
-    }
-    Dft<N2, 1, double>::run(x);
-#pragma unroll
-    for (int n2 = 1; n2 < N2; ++n2) {
-      const int e = (n2 * k1) % N;
-      const cx<double> w = TG ? cx<double>{groots[2 * e], groots[2 * e + 1]} : roots[rix(e)];
-      x[n2] = cx_rot(x[n2], w.re, -w.im);
-    }
-#pragma unroll
-    for (int i = 0; i < N2; ++i) buf[l * LSZ + k1 * PS + i] = x[i];
-  }
-  __syncthreads();
-
-  // step A': inverse length-N1 transforms
-  for (int job = tid; job < kLP * N2; job += NTH) {
-    const int l = job / N2, n2 = job % N2;
-    cx<double> x[N1];
-#pragma unroll
-    for (int i = 0; i < N1; ++i) x[i] = buf[l * LSZ + i * PS + n2];
-    Dft<N1, 1, double>::run(x);
-#pragma unroll
-    for (int i = 0; i < N1; ++i) buf[l * LSZ + i * PS + n2] = x[i];
-  }
-  __syncthreads();
-
-  if (ADJ) {
-    // fold the extension region back onto the 2d matching points (transpose
-    // of the continuation): column c of the continuation matrix
-    for (int t = tid; t < kLP * 2 * dd; t += NTH) {
-      const int l = t / (2 * dd), c = t % (2 * dd);
-      double sr = 0.0, si = 0.0;
-#pragma unroll 4
-      for (int p = 0; p < CE; ++p) {
-        const double mv = Mx[p * 2 * dd + c];
-        const cx<double> y = buf[l * LSZ + ph(n + p)];
-        sr += mv * y.re;
-        si += mv * y.im;
-      }
-      fold[l * 2 * kMaxFcD + c] = {sr, si};
-    }
-    __syncthreads();
-  }
-
-  // epilogue: scale (forward) or add the fold (transpose) and store
-  double c4[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) c4[r] = ADJ ? 1.0 : -a.coef[d.dir][d.s0 + r];
-  T* out = a.out[d.dir] + d.base;
-  const int64_t ls = a.line_stride[d.dir], ps = a.pt_stride[d.dir];
-  constexpr int TMAX = (2 * N + NTH - 1) / NTH;
-#pragma unroll
-  for (int t = 0; t < TMAX; ++t) {
-    const int e = tid + NTH * t, it = e & 1, i = e >> 1;
-    if (i < n && (it == 0 || d.has1)) {
-      const cx<double> z0 = buf[(2 * it) * LSZ + ph(i)], z1 = buf[(2 * it + 1) * LSZ + ph(i)];
-      double dv[4] = {z0.re, z0.im, z1.re, z1.im};
-      if (ADJ) {
-        if (i >= n - dd) {
-          const cx<double> f0 = fold[(2 * it) * 2 * kMaxFcD + (i - (n - dd))];
-          const cx<double> f1 = fold[(2 * it + 1) * 2 * kMaxFcD + (i - (n - dd))];
-          dv[0] += f0.re; dv[1] += f0.im; dv[2] += f1.re; dv[3] += f1.im;
-        }
-        if (i < dd) {
-          const cx<double> f0 = fold[(2 * it) * 2 * kMaxFcD + dd + (dd - 1 - i)];
-          const cx<double> f1 = fold[(2 * it + 1) * 2 * kMaxFcD + dd + (dd - 1 - i)];
-          dv[0] += f0.re; dv[1] += f0.im; dv[2] += f1.re; dv[3] += f1.im;
-        }
-      }
-      T* q = out + it * ls + (int64_t)i * ps;
-      if constexpr (sizeof(T) == 8) {
-        reinterpret_cast<double2*>(q)[0] = make_double2(c4[0] * dv[0], c4[1] * dv[1]);
-        reinterpret_cast<double2*>(q)[1] = make_double2(c4[2] * dv[2], c4[3] * dv[3]);
-      } else {
-        *reinterpret_cast<float4*>(q) =
-            make_float4(float(c4[0] * dv[0]), float(c4[1] * dv[1]), float(c4[2] * dv[2]), float(c4[3] * dv[3]));
-      }
-    }
-  }
-}
-
-// Issue the loads of the FC tables into registers (kept until staged).
-template <int N, int NTH, bool TG>
-struct TabRegs {
-  static constexpr int RT = TG ? 1 : (N + NTH - 1) / NTH, MT = TG ? 1 : (N + NTH - 1) / NTH,
-                       XT = (kFcTab + NTH - 1) / NTH;
-  double rr[RT][2], mm[MT], xx[XT];
-  __device__ __forceinline__ void load(const FcPlanDev& fc, int lane) {
-    const int nmx = 2 * fc.d * (fc.C + fc.E);
-    if (!TG) {
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int k = lane + NTH * t;
-        rr[t][0] = (k < N) ? fc.roots[2 * k] : 0.0;
-        rr[t][1] = (k < N) ? fc.roots[2 * k + 1] : 0.0;
-      }
-#pragma unroll
-      for (int t = 0; t < MT; ++t) {
-        const int k = lane + NTH * t;
-        mm[t] = (k < N) ? fc.mu[k] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < XT; ++t) {
-      const int k = lane + NTH * t;
-      xx[t] = (k < nmx) ? fc.Mx[k] : 0.0;
-    }
-  }
-  __device__ __forceinline__ void stage(cx<double>* roots, double* mu, double* Mx, int nmx, int lane) const {
-    if (!TG) {
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int k = lane + NTH * t;
-        if (k < N) roots[rix(k)] = {rr[t][0], rr[t][1]};
-      }
-#pragma unroll
-      for (int t = 0; t < MT; ++t) {
-        const int k = lane + NTH * t;
-        if (k < N) mu[k] = mm[t];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < XT; ++t) {
-      const int k = lane + NTH * t;
-      if (k < nmx) Mx[k] = xx[t];
-    }
-  }
-};
-
-// A workgroup of NW waves (NTH = 64 NW threads) transforms one unit at a
-// time.  UPW = 2: the workgroup's two units and the tables are all loaded
-// before the first transform.  UPW = 1 (also for long lines, whose loads alone
-// would fill the register file): tables first, then the unit in chunks of
-// 8 load slots per thread.
-template <typename T, bool ADJ, int N1, int N2, int UPW, int NW, bool TG>
-__global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
-  constexpr int N = N1 * N2;
-  constexpr int NTH = 64 * NW;
-  constexpr int TMAX = (2 * N + NTH - 1) / NTH;
-  typedef L4Smem<N1, N2> SM;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* sm = reinterpret_cast<double*>(smem_raw);
-  cx<double>* buf = reinterpret_cast<cx<double>*>(sm);
-  cx<double>* fold = reinterpret_cast<cx<double>*>(sm + SM::BUF);
-  cx<double>* roots = reinterpret_cast<cx<double>*>(sm + SM::BUF + SM::FOLD);
-  double* mu = sm + SM::BUF + SM::FOLD + SM::ROOTS;
-  double* Mx = sm + SM::mx_off(TG);
-
-  const FcPlanDev& fc = a.fc;
-  const int n = fc.n, dd = fc.d, CE = fc.C + fc.E;
-  const int tid = threadIdx.x;
-
-  if constexpr (UPW == 2) {
-    const UnitDesc d0 = decode_unit(a, 2 * (int)blockIdx.x);
-    const UnitDesc d1 = decode_unit(a, 2 * (int)blockIdx.x + 1);
-    UnitRegs<T, TMAX> R0, R1;
-    load_unit<T, TMAX, NTH>(a, d0, n, tid, R0);
-    load_unit<T, TMAX, NTH>(a, d1, n, tid, R1);
-    TabRegs<N, NTH, TG> tab;
-    tab.load(fc, tid);
-    tab.stage(roots, mu, Mx, 2 * dd * CE, tid);
-    if (d0.live) {
-      stage_unit<T, TMAX, N1, N2, NTH>(R0, d0, a.coef[d0.dir], ADJ, n, tid, buf);
-      __syncthreads();
-      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, fold, roots, mu, Mx);
-    }
-    if (d1.live) {
-      __syncthreads();
-      stage_unit<T, TMAX, N1, N2, NTH>(R1, d1, a.coef[d1.dir], ADJ, n, tid, buf);
-      __syncthreads();
-      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d1, n, dd, CE, tid, buf, fold, roots, mu, Mx);
-    }
-  } else {
-    const UnitDesc d0 = decode_unit(a, remap_unit16((int)blockIdx.x));
-    if (!d0.live) return;
-    {
-      TabRegs<N, NTH, TG> tab;
-      tab.load(fc, tid);
-      tab.stage(roots, mu, Mx, 2 * dd * CE, tid);
-    }
-    constexpr int CH = 8;
-    for (int c0 = 0; c0 < TMAX; c0 += CH) {
-      UnitRegs<T, CH> R;
-      const T* in = a.in + d0.base;
-      const int64_t ls = a.line_stride[d0.dir], ps = a.pt_stride[d0.dir];
-#pragma unroll
-      for (int t = 0; t < CH; ++t) {
-        const int e = tid + NTH * (c0 + t), it = e & 1, i = e >> 1;
-        if (c0 + t < TMAX && i < n && (it == 0 || d0.has1)) {
-          const T* p = in + it * ls + (int64_t)i * ps;
-          if constexpr (sizeof(T) == 8) {
-            const double2 x = reinterpret_cast<const double2*>(p)[0];
-            const double2 y = reinterpret_cast<const double2*>(p)[1];
-            R.v[t][0] = x.x; R.v[t][1] = x.y; R.v[t][2] = y.x; R.v[t][3] = y.y;
-          } else {
-            const float4 x = *reinterpret_cast<const float4*>(p);
-            R.v[t][0] = x.x; R.v[t][1] = x.y; R.v[t][2] = x.z; R.v[t][3] = x.w;
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) R.v[t][r] = T(0);
-        }
-      }
-      const double* cf = a.coef[d0.dir];
-#pragma unroll
-      for (int t = 0; t < CH; ++t) {
-        const int e = tid + NTH * (c0 + t), it = e & 1, i = e >> 1;
-        if (c0 + t < TMAX && i < n) {
-          const int ph = (i / N2) * SM::PS + i % N2;
-          const double f0 = ADJ ? cf[d0.s0] : 1.0, f1 = ADJ ? cf[d0.s0 + 1] : 1.0;
-          const double f2 = ADJ ? cf[d0.s0 + 2] : 1.0, f3 = ADJ ? cf[d0.s0 + 3] : 1.0;
-          buf[(2 * it) * SM::LSZ + ph] = {f0 * (double)R.v[t][0], f1 * (double)R.v[t][1]};
-          buf[(2 * it + 1) * SM::LSZ + ph] = {f2 * (double)R.v[t][2], f3 * (double)R.v[t][3]};
-        }
-      }
-    }
-    if (ADJ) {
-      const int ext = N - n;
-      for (int e = tid; e < kLP * ext; e += NTH) {
-        const int l = e / ext, i = n + e % ext;
-        buf[l * SM::LSZ + (i / N2) * SM::PS + i % N2] = {0.0, 0.0};
-      }
-    }
-    __syncthreads();
-    transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, fold, roots, mu, Mx);
-  }
-}
-
+// N_p = N1 x N2 with both factors products of 2, 3, 4, 5 (register codelets)
+// and at most 32 (one pass over the lanes of a two-wave workgroup).
 bool fourstep_split(int Np, int* n1, int* n2) {
   switch (Np) {
+    case 45: *n1 = 5; *n2 = 9; return true;
+    case 48: *n1 = 6; *n2 = 8; return true;
+    case 50: *n1 = 5; *n2 = 10; return true;
+    case 54: *n1 = 6; *n2 = 9; return true;
+    case 60: *n1 = 6; *n2 = 10; return true;
+    case 64: *n1 = 8; *n2 = 8; return true;
+    case 72: *n1 = 8; *n2 = 9; return true;
+    case 75: *n1 = 5; *n2 = 15; return true;
+    case 80: *n1 = 8; *n2 = 10; return true;
+    case 81: *n1 = 9; *n2 = 9; return true;
     case 90: *n1 = 9; *n2 = 10; return true;
+    case 96: *n1 = 8; *n2 = 12; return true;
+    case 100: *n1 = 10; *n2 = 10; return true;
+    case 108: *n1 = 9; *n2 = 12; return true;
+    case 120: *n1 = 10; *n2 = 12; return true;
+    case 125: *n1 = 5; *n2 = 25; return true;
+    case 128: *n1 = 8; *n2 = 16; return true;
+    case 135: *n1 = 9; *n2 = 15; return true;
+    case 144: *n1 = 12; *n2 = 12; return true;
+    case 150: *n1 = 10; *n2 = 15; return true;
     case 160: *n1 = 16; *n2 = 10; return true;
+    case 162: *n1 = 9; *n2 = 18; return true;
+    case 180: *n1 = 12; *n2 = 15; return true;
+    case 192: *n1 = 12; *n2 = 16; return true;
+    case 200: *n1 = 10; *n2 = 20; return true;
+    case 216: *n1 = 12; *n2 = 18; return true;
+    case 225: *n1 = 15; *n2 = 15; return true;
+    case 240: *n1 = 15; *n2 = 16; return true;
+    case 243: *n1 = 9; *n2 = 27; return true;
+    case 250: *n1 = 10; *n2 = 25; return true;
+    case 256: *n1 = 16; *n2 = 16; return true;
+    case 270: *n1 = 15; *n2 = 18; return true;
     case 288: *n1 = 16; *n2 = 18; return true;
+    case 300: *n1 = 15; *n2 = 20; return true;
+    case 320: *n1 = 16; *n2 = 20; return true;
+    case 324: *n1 = 18; *n2 = 18; return true;
+    case 360: *n1 = 18; *n2 = 20; return true;
+    case 375: *n1 = 15; *n2 = 25; return true;
+    case 384: *n1 = 16; *n2 = 24; return true;
+    case 400: *n1 = 20; *n2 = 20; return true;
+    case 405: *n1 = 15; *n2 = 27; return true;
+    case 432: *n1 = 18; *n2 = 24; return true;
+    case 450: *n1 = 18; *n2 = 25; return true;
+    case 480: *n1 = 20; *n2 = 24; return true;
+    case 486: *n1 = 18; *n2 = 27; return true;
+    case 500: *n1 = 20; *n2 = 25; return true;
+    case 512: *n1 = 16; *n2 = 32; return true;
     case 540: *n1 = 20; *n2 = 27; return true;
+    case 576: *n1 = 24; *n2 = 24; return true;
+    case 600: *n1 = 24; *n2 = 25; return true;
     default: return false;
   }
-}
-
-// Two units per workgroup only where both units' loads fit in registers.
-template <int N1, int N2, int NW>
-constexpr bool kPairOk = (2 * N1 * N2 + 64 * NW - 1) / (64 * NW) <= 9;
-
-template <typename T, bool ADJ, int N1, int N2, int NW, bool TG>
-static hipError_t go_nw(const Lines4Args<T>& a, int upw, hipStream_t s) {
-  const size_t sh = L4Smem<N1, N2>::bytes(2 * a.fc.d * (a.fc.C + a.fc.E), TG);
-  if (sh > kLines4MaxLds) return hipErrorNotSupported;
-  if constexpr (kPairOk<N1, N2, NW>) {
-    if (upw == 2) {
-      const int groups = (a.nunits + 1) / 2;
-      if (groups == 0) return hipSuccess;
-      hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, 2, NW, TG>), dim3((unsigned)groups), dim3(64 * NW), sh, s, a);
-      return hipGetLastError();
-    }
-  }
-  if (a.nunits == 0) return hipSuccess;
-  const int groups = ((a.nunits + 15) / 16) * 16;
-  hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, 1, NW, TG>), dim3((unsigned)groups), dim3(64 * NW), sh, s, a);
-  return hipGetLastError();
 }
 
 template <typename T, bool ADJ, int N1, int N2>
@@ -514,7 +75,13 @@ static hipError_t by_size(const Lines4Args<T>& a, int upw, int nw, int tg, hipSt
     case 160: return go<T, ADJ, 16, 10>(a, upw, nw, tg, s);
     case 288: return go<T, ADJ, 16, 18>(a, upw, nw, tg, s);
     case 540: return go<T, ADJ, 20, 27>(a, upw, nw, tg, s);
-    default: return hipErrorNotSupported;
+    default: {
+      hipError_t e = lines4_extra0(a, ADJ, s);
+      if (e == hipErrorNotSupported) e = lines4_extra1(a, ADJ, s);
+      if (e == hipErrorNotSupported) e = lines4_extra2(a, ADJ, s);
+      if (e == hipErrorNotSupported) e = lines4_extra3(a, ADJ, s);
+      return e;
+    }
   }
 }
 

@@ -88,7 +88,7 @@ struct Plan {
   int64_t grp_stride = 0;   // ny * nxp * kGroup elements
   int64_t inst_stride = 0;  // G * grp_stride
   bool fc_same = false;     // x and y FC plans identical: both line sets in one launch
-  rte_schedule sched{2, 0, 0, 1, 0, 0};  // launch schedule (node_tiles_per_block resolved at create)
+  rte_schedule sched{1, 0, 0, 2, 1, 0};  // launch schedule (node_tiles_per_block resolved at create)
   int64_t sched_version = 0;       // bumped by every schedule change (graph keys)
   int64_t nb = 0;     // boundary nodes 2(nx+ny)-4
   int64_t npos = 0;   // max(nx, ny)
