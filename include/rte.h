@@ -78,6 +78,13 @@ typedef struct {
   int64_t ckpt_every;       /* 0: keep every state u^0..u^K for the adjoint;
                                s > 0: keep checkpoints every s steps and replay
                                segments of s steps during the adjoint              */
+  int64_t combo_chunk;      /* generalised sources solved together (0: all Nq).
+                               With c < Nq the workspace holds the states of c
+                               sources; rte_gradient runs forward, misfit and
+                               adjoint chunk by chunk (the misfit and the
+                               gradient are sums over sources), and rte_adjoint
+                               recomputes the forward of every chunk but the
+                               last one rte_forward left in the workspace.       */
 } rte_problem;
 
 /* A laser beam, eq. (RTEsources2)/(sourcelab):

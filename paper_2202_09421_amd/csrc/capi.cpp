@@ -91,21 +91,36 @@ int adj_step(Ctx& c, int n, const void* un) {
   return RTE_OK;
 }
 
-int run_forward(Plan& p, const void* mu_a, const void* mu_s, double* G, void* u_final, int save, void* wsp,
-                int64_t wsb, hipStream_t st) {
-  Workspace ws;
-  if (!map_workspace(p, wsp, wsb, save != 0, &ws)) {
-    std::ostringstream o;
-    o << "workspace too small: need " << workspace_bytes(p, save != 0) << " bytes";
-    set_error(o.str());
-    return RTE_ENOMEM;
-  }
-  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
-  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
-  Ctx c{p, ws, st, mu_a, mu_s, S};
-  p.have_forward = false;
+// Sources are solved in chunks of p.chunk (one chunk when the workspace holds
+// them all).  Chunk k covers sources [k chunk, min((k + 1) chunk, Nq)).
+int64_t n_chunks(const Plan& p) { return (p.Nq + p.chunk - 1) / p.chunk; }
+
+void set_chunk(const Plan& p, int64_t k) {
+  p.cq0 = k * p.chunk;
+  p.cnq = std::min(p.chunk, p.Nq - p.cq0);
+}
+
+void reset_chunk(const Plan& p) {
+  p.cq0 = 0;
+  p.cnq = p.chunk;
+}
+
+bool map_or_fail(const Plan& p, void* wsp, int64_t wsb, bool adj, Workspace* ws) {
+  if (map_workspace(p, wsp, wsb, adj, ws)) return true;
+  std::ostringstream o;
+  o << "workspace too small: need " << workspace_bytes(p, adj) << " bytes";
+  set_error(o.str());
+  return false;
+}
+
+// Time loop of the forward for the current chunk (u^0 = 0, zero history);
+// writes the chunk's detector flux; keeps states or checkpoints when save.
+int forward_chunk(Ctx& c, bool save, void* u_final) {
+  Plan& p = c.p;
+  Workspace& ws = c.ws;
+  hipStream_t st = c.st;
+  const int64_t S = c.S;
   for (int k = 0; k < 3; ++k) RTE_CHECK(launch_zero(ws.lring[k], S, st));
-  RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
   const bool store_all = save && p.ckpt_every == 0;
   const int64_t s = p.ckpt_every;
   void* u0 = store_all ? ws.states : ws.work_u[0];
@@ -124,39 +139,24 @@ int run_forward(Plan& p, const void* mu_a, const void* mu_s, double* G, void* u_
     if (rc != RTE_OK) return rc;
     un = unp1;
   }
-  if (G) RTE_CHECK(launch_detect(p, ws.flux, G, (int)p.K, st));
   if (u_final) RTE_CHECK(launch_unpermute(p, un, u_final, st));
-  p.have_forward = save != 0;
-  p.saved_K = p.K;
   return RTE_OK;
 }
 
-int run_adjoint(Plan& p, const void* mu_a, const void* mu_s, const double* Gbar, double* da, double* db, void* wsp,
-                int64_t wsb, hipStream_t st) {
-  if (!p.have_forward) {
-    set_error("rte_adjoint needs a preceding rte_forward with save_states=1 on this plan");
-    return RTE_ESTATE;
-  }
-  Workspace ws;
-  if (!map_workspace(p, wsp, wsb, true, &ws)) {
-    std::ostringstream o;
-    o << "workspace too small: need " << workspace_bytes(p, true) << " bytes";
-    set_error(o.str());
-    return RTE_ENOMEM;
-  }
-  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
-  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
-  Ctx c{p, ws, st, mu_a, mu_s, S};
+// Reverse time loop of the adjoint for the current chunk, whose forward
+// states (or checkpoints) are in the workspace and whose detector injection
+// is in ws.flux; accumulates the chunk's gradient partials into ga, gb.
+int adjoint_chunk(Ctx& c) {
+  Plan& p = c.p;
+  Workspace& ws = c.ws;
+  hipStream_t st = c.st;
+  const int64_t S = c.S;
   const int K = (int)p.K;
-  RTE_CHECK(launch_inject(p, Gbar, ws.flux, K, st));
   // zero adjoint ring and carries: ubar^{K+1} = 0, v^{K+2..K+4} = 0
   for (int k = 0; k < 4; ++k) RTE_CHECK(launch_zero(ws.vring[k], S, st));
   RTE_CHECK(launch_zero(ws.atx, S, st));
   RTE_CHECK(launch_zero(ws.aty, S, st));
   RTE_CHECK(launch_zero(ws.ap1, S, st));
-  const int64_t gbytes = p.Nq * p.nx * p.ny * 8;
-  RTE_CHECK(launch_zero(ws.ga, gbytes, st));
-  RTE_CHECK(launch_zero(ws.gb, gbytes, st));
   if (p.ckpt_every == 0) {
     for (int n = K; n >= 1; --n) {
       int rc = adj_step(c, n, at(ws.states, n, S));
@@ -182,6 +182,67 @@ int run_adjoint(Plan& p, const void* mu_a, const void* mu_s, const double* Gbar,
       }
     }
   }
+  return RTE_OK;
+}
+
+int run_forward(Plan& p, const void* mu_a, const void* mu_s, double* G, void* u_final, int save, void* wsp,
+                int64_t wsb, hipStream_t st) {
+  Workspace ws;
+  if (!map_or_fail(p, wsp, wsb, save != 0, &ws)) return RTE_ENOMEM;
+  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
+  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  Ctx c{p, ws, st, mu_a, mu_s, S};
+  p.have_forward = false;
+  RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
+  const int64_t nc = n_chunks(p);
+  for (int64_t k = 0; k < nc; ++k) {
+    set_chunk(p, k);
+    int rc = forward_chunk(c, save != 0, u_final);
+    if (rc == RTE_OK && G) rc = launch_detect(p, ws.flux, G, (int)p.K, st) == hipSuccess ? RTE_OK : RTE_EDEVICE;
+    if (rc != RTE_OK) {
+      reset_chunk(p);
+      if (rc == RTE_EDEVICE && last_error()[0] == '\0') set_error("detector kernel launch failed");
+      return rc;
+    }
+  }
+  reset_chunk(p);
+  p.have_forward = save != 0;
+  p.saved_chunk = save ? nc - 1 : -1;
+  p.saved_K = p.K;
+  return RTE_OK;
+}
+
+// Adjoint of the last saved forward.  The chunk whose states are in the
+// workspace goes first; every other chunk's forward is recomputed.
+int run_adjoint(Plan& p, const void* mu_a, const void* mu_s, const double* Gbar, double* da, double* db, void* wsp,
+                int64_t wsb, hipStream_t st) {
+  if (!p.have_forward) {
+    set_error("rte_adjoint needs a preceding rte_forward with save_states=1 on this plan");
+    return RTE_ESTATE;
+  }
+  Workspace ws;
+  if (!map_or_fail(p, wsp, wsb, true, &ws)) return RTE_ENOMEM;
+  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
+  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  Ctx c{p, ws, st, mu_a, mu_s, S};
+  const int64_t gbytes = p.Nq * p.nx * p.ny * 8;
+  RTE_CHECK(launch_zero(ws.ga, gbytes, st));
+  RTE_CHECK(launch_zero(ws.gb, gbytes, st));
+  const int64_t nc = n_chunks(p);
+  for (int64_t i = 0; i < nc; ++i) {
+    const int64_t k = (p.saved_chunk + nc - i) % nc;  // saved chunk first
+    set_chunk(p, k);
+    int rc = (i == 0) ? RTE_OK : forward_chunk(c, true, nullptr);
+    if (rc == RTE_OK && launch_inject(p, Gbar, ws.flux, (int)p.K, st) != hipSuccess) rc = RTE_EDEVICE;
+    if (rc == RTE_OK) rc = adjoint_chunk(c);
+    if (rc != RTE_OK) {
+      reset_chunk(p);
+      if (rc == RTE_EDEVICE && last_error()[0] == '\0') set_error("injection kernel launch failed");
+      return rc;
+    }
+  }
+  p.saved_chunk = (p.saved_chunk + 1) % nc;  // the last chunk processed
+  reset_chunk(p);
   RTE_CHECK(launch_grad_reduce(p, ws.ga, ws.gb, da, db, st));
   return RTE_OK;
 }
@@ -198,14 +259,44 @@ struct GradArgs {
   int64_t wsb;
 };
 
-// Forward with kept states, misfit and cotangent, adjoint: all enqueued on st.
+// Forward with kept states, misfit and cotangent, adjoint, chunk by chunk:
+// all enqueued on st.
 int enqueue_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
-  int rc = run_forward(p, a.mu_a, a.mu_s, a.G, nullptr, 1, a.ws, a.wsb, st);
-  if (rc != RTE_OK) return rc;
   Workspace ws;
-  map_workspace(p, a.ws, a.wsb, true, &ws);
-  RTE_CHECK(launch_misfit(p, a.G, a.G_meas, ws.gbar, a.J, (int)p.K, st));
-  return run_adjoint(p, a.mu_a, a.mu_s, ws.gbar, a.dmu_a, a.dmu_s, a.ws, a.wsb, st);
+  if (!map_or_fail(p, a.ws, a.wsb, true, &ws)) return RTE_ENOMEM;
+  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
+  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  Ctx c{p, ws, st, a.mu_a, a.mu_s, S};
+  p.have_forward = false;
+  RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
+  const int64_t gbytes = p.Nq * p.nx * p.ny * 8;
+  RTE_CHECK(launch_zero(ws.ga, gbytes, st));
+  RTE_CHECK(launch_zero(ws.gb, gbytes, st));
+  const int64_t nc = n_chunks(p);
+  const int K = (int)p.K;
+  for (int64_t k = 0; k < nc; ++k) {
+    set_chunk(p, k);
+    int rc = forward_chunk(c, true, nullptr);
+    hipError_t e = hipSuccess;
+    if (rc == RTE_OK) e = launch_detect(p, ws.flux, a.G, K, st);
+    if (rc == RTE_OK && e == hipSuccess) e = launch_misfit(p, a.G, a.G_meas, ws.gbar, a.J, K, st);
+    if (rc == RTE_OK && e == hipSuccess) e = launch_inject(p, ws.gbar, ws.flux, K, st);
+    if (rc == RTE_OK && e != hipSuccess) {
+      set_error(std::string("detector/misfit kernel launch failed: ") + hipGetErrorString(e));
+      rc = RTE_EDEVICE;
+    }
+    if (rc == RTE_OK) rc = adjoint_chunk(c);
+    if (rc != RTE_OK) {
+      reset_chunk(p);
+      return rc;
+    }
+  }
+  reset_chunk(p);
+  RTE_CHECK(launch_grad_reduce(p, ws.ga, ws.gb, a.dmu_a, a.dmu_s, st));
+  p.have_forward = true;
+  p.saved_chunk = nc - 1;
+  p.saved_K = p.K;
+  return RTE_OK;
 }
 
 // Graph mode: record the whole sequence once per argument set, then replay.

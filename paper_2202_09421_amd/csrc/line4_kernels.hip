@@ -109,7 +109,7 @@ static hipError_t launch4_t(const Plan& p, const LineLaunch& L, hipStream_t s) {
   const bool dx = (L.dirs & 1) != 0, dy = (L.dirs & 2) != 0;
   a.dir_first = dx ? 0 : 1;
   a.fc = dx ? p.fcx : p.fcy;
-  const int64_t per = p.Nq * p.G;
+  const int64_t per = p.cnq * p.G;
   a.units_first = (int)(per * a.npe[a.dir_first]);
   a.nunits = a.units_first + ((dx && dy) ? (int)(per * a.npe[1]) : 0);
   const int upw = p.sched.line_units_per_wave, nw = p.sched.line_waves_per_unit, tg = p.sched.line_global_tables;

@@ -238,7 +238,7 @@ static hipError_t launch_mode(const Plan& p, const void* in, void* out, int dir,
   }
   const int Np = a.fc.Np;
   const size_t shmem = line_shmem_bytes(Np, p.dtype);
-  dim3 grid((unsigned)(((a.nlines + 31) / 32) * 32), (unsigned)p.G, (unsigned)p.Nq);
+  dim3 grid((unsigned)(((a.nlines + 31) / 32) * 32), (unsigned)p.G, (unsigned)p.cnq);
   hipLaunchKernelGGL((line_kernel<T, adj>), grid, dim3(kLineThreads), shmem, s, a);
   return hipGetLastError();
 }

@@ -65,6 +65,7 @@ struct Mfma<float> {
 // for RT >= 5 (NT = 1).
 struct NodeGeom {
   int nx, ny, nxp, M, Mpad, G, nb, npos, K1, RT, NT, npos_total;
+  int q0;                   // first source of the chunk (blockIdx.y is the source within it)
   int ntiles, tile_shift;   // tiles are visited from the one holding the last row's start
   int64_t grp_stride, inst_stride;
 };
@@ -171,8 +172,8 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
   const TileLane t = tile_lane(G);
   T* Bs = reinterpret_cast<T*>(smem_raw) + (size_t)t.nt * G.Mpad * 16;
   double* Fx = reinterpret_cast<double*>(smem_raw + ((sizeof(T) * (size_t)G.NT * G.Mpad * 16 + 15) & ~size_t(15)));
-  const int q = blockIdx.y;
-  const int64_t ib = (int64_t)q * G.inst_stride;
+  const int q = G.q0 + (int)blockIdx.y;   // source (beams, detector flux)
+  const int64_t ib = (int64_t)blockIdx.y * G.inst_stride;
 
   const T* uq = a.u + ib;
   const T* Xq = a.X + ib;
@@ -307,8 +308,8 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
   const TileLane t = tile_lane(G);
   T* Bs = reinterpret_cast<T*>(smem_raw) + (size_t)t.nt * G.Mpad * 16;
   double* Fx = reinterpret_cast<double*>(smem_raw + ((sizeof(T) * (size_t)G.NT * G.Mpad * 16 + 15) & ~size_t(15)));
-  const int q = blockIdx.y;
-  const int64_t ib = (int64_t)q * G.inst_stride;
+  const int q = G.q0 + (int)blockIdx.y;   // source (injection, gradient maps)
+  const int64_t ib = (int64_t)blockIdx.y * G.inst_stride;
   const int Nn = G.nx * G.ny;
 
   const T* txq = a.atx + ib;
@@ -442,6 +443,7 @@ static NodeGeom make_geom(const Plan& p) {
   g.RT = (int)(p.Mpad / 16);
   g.NT = p.sched.node_tiles_per_block;
   g.npos_total = (int)(p.ny * p.nxp);
+  g.q0 = (int)p.cq0;
   g.ntiles = (g.npos_total + 15) / 16;
   g.tile_shift = (int)((p.ny - 1) * p.nxp / 16);
   g.grp_stride = p.grp_stride;
@@ -466,7 +468,7 @@ static size_t node_shmem(const NodeGeom& g, size_t es) {
 
 static dim3 node_grid(const Plan& p, const NodeGeom& g) {
   const int tiles = (g.npos_total + 15) / 16;
-  return dim3((unsigned)((tiles + g.NT - 1) / g.NT), (unsigned)p.Nq);
+  return dim3((unsigned)((tiles + g.NT - 1) / g.NT), (unsigned)p.cnq);
 }
 
 template <typename T>
@@ -526,10 +528,11 @@ hipError_t launch_node_adj(const Plan& p, const NodeAdjLaunch& L, hipStream_t s)
 
 // G[q][jd][k] = sum_{w,pos} det_w[jd][w][pos] flux[q][k+1][w][pos]
 __global__ void detect_kernel(const double* __restrict__ flux, const double* __restrict__ dw, double* __restrict__ G,
-                              int Nq, int Nd, int K, int npos) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                              int q0, int Nq, int Nd, int K, int npos) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)Nq * Nd * K;
-  if (t >= total) return;
+  if (t0 >= total) return;
+  const int64_t t = t0 + (int64_t)q0 * Nd * K;
   const int k = (int)(t % K);
   const int jd = (int)((t / K) % Nd);
   const int q = (int)(t / ((int64_t)K * Nd));
@@ -542,11 +545,11 @@ __global__ void detect_kernel(const double* __restrict__ flux, const double* __r
 
 // inj[q][n][w][pos] = sum_jd det_w[jd][w][pos] Gbar[q][jd][n-1], n = 1..K
 __global__ void inject_kernel(const double* __restrict__ Gbar, const double* __restrict__ dw, double* __restrict__ inj,
-                              int Nq, int Nd, int K, int npos) {
+                              int q0, int Nq, int Nd, int K, int npos) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per = (int64_t)K * 4 * npos;
   if (t >= (int64_t)Nq * per) return;
-  const int q = (int)(t / per);
+  const int q = q0 + (int)(t / per);
   const int64_t r = t % per;
   const int n = 1 + (int)(r / (4 * npos));
   const int x = (int)(r % (4 * npos));
@@ -555,10 +558,11 @@ __global__ void inject_kernel(const double* __restrict__ Gbar, const double* __r
   inj[((int64_t)q * (K + 1) + n) * 4 * npos + x] = acc;
 }
 
-// Gbar = dt (G - Gm); J = 1/2 dt sum (G - Gm)^2 (one block, fixed reduction order)
+// Gbar = dt (G - Gm); J (+)= 1/2 dt sum (G - Gm)^2 over n entries (one block,
+// fixed reduction order; accumulate adds to J, for the chunks after the first)
 __global__ __launch_bounds__(1024) void misfit_kernel(const double* __restrict__ G, const double* __restrict__ Gm,
                                                       double* __restrict__ Gbar, double* __restrict__ J, int64_t n,
-                                                      double dt) {
+                                                      double dt, int accumulate) {
   __shared__ double red[1024];
   double acc = 0.0;
   for (int64_t t = threadIdx.x; t < n; t += 1024) {
@@ -572,7 +576,7 @@ __global__ __launch_bounds__(1024) void misfit_kernel(const double* __restrict__
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *J = 0.5 * dt * red[0];
+  if (threadIdx.x == 0) *J = (accumulate ? *J : 0.0) + 0.5 * dt * red[0];
 }
 
 __global__ void grad_reduce_kernel(const double* __restrict__ ga, const double* __restrict__ gb, double* __restrict__ da,
@@ -629,25 +633,28 @@ hipError_t launch_copy(void* d, const void* src, int64_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
+// detect, inject and misfit work on the sources of the current chunk
 hipError_t launch_detect(const Plan& p, const double* flux, double* G, int K, hipStream_t s) {
-  const int64_t total = p.Nq * p.Nd * K;
+  const int64_t total = p.cnq * p.Nd * K;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(detect_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, flux, p.dev.det_w, G,
-                     (int)p.Nq, (int)p.Nd, K, (int)p.npos);
+                     (int)p.cq0, (int)p.cnq, (int)p.Nd, K, (int)p.npos);
   return hipGetLastError();
 }
 
 hipError_t launch_inject(const Plan& p, const double* Gbar, double* inj, int K, hipStream_t s) {
-  const int64_t total = p.Nq * (int64_t)K * 4 * p.npos;
+  const int64_t total = p.cnq * (int64_t)K * 4 * p.npos;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(inject_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, Gbar, p.dev.det_w, inj,
-                     (int)p.Nq, (int)p.Nd, K, (int)p.npos);
+                     (int)p.cq0, (int)p.cnq, (int)p.Nd, K, (int)p.npos);
   return hipGetLastError();
 }
 
 hipError_t launch_misfit(const Plan& p, const double* G, const double* Gm, double* Gbar, double* J, int K,
                          hipStream_t s) {
-  hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(1024), 0, s, G, Gm, Gbar, J, p.Nq * p.Nd * (int64_t)K, p.prob.dt);
+  const int64_t off = p.cq0 * p.Nd * (int64_t)K;
+  hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(1024), 0, s, G + off, Gm + off, Gbar + off, J,
+                     p.cnq * p.Nd * (int64_t)K, p.prob.dt, p.cq0 > 0 ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -659,16 +666,18 @@ hipError_t launch_grad_reduce(const Plan& p, const double* ga, const double* gb,
   return hipGetLastError();
 }
 
+// the chunk's sources into out[cq0 .. cq0 + cnq)
 hipError_t launch_unpermute(const Plan& p, const void* state, void* out, hipStream_t s) {
   const int64_t Nn = p.nx * p.ny;
-  const int64_t total = p.Nq * Nn * p.M;
+  const int64_t total = p.cnq * Nn * p.M;
   const dim3 grid((unsigned)((total + 255) / 256));
+  const int64_t off = p.cq0 * Nn * p.M;
   if (p.dtype == RTE_F64)
-    hipLaunchKernelGGL(unpermute_kernel<double>, grid, dim3(256), 0, s, (const double*)state, (double*)out,
-                       p.dev.slot_m, (int)p.M, (int)p.nx, (int)p.nxp, Nn, (int)p.Nq, p.grp_stride, p.inst_stride);
+    hipLaunchKernelGGL(unpermute_kernel<double>, grid, dim3(256), 0, s, (const double*)state, (double*)out + off,
+                       p.dev.slot_m, (int)p.M, (int)p.nx, (int)p.nxp, Nn, (int)p.cnq, p.grp_stride, p.inst_stride);
   else
-    hipLaunchKernelGGL(unpermute_kernel<float>, grid, dim3(256), 0, s, (const float*)state, (float*)out,
-                       p.dev.slot_m, (int)p.M, (int)p.nx, (int)p.nxp, Nn, (int)p.Nq, p.grp_stride, p.inst_stride);
+    hipLaunchKernelGGL(unpermute_kernel<float>, grid, dim3(256), 0, s, (const float*)state, (float*)out + off,
+                       p.dev.slot_m, (int)p.M, (int)p.nx, (int)p.nxp, Nn, (int)p.cnq, p.grp_stride, p.inst_stride);
   return hipGetLastError();
 }
 

@@ -199,6 +199,7 @@ static bool validate(const rte_problem* p, const rte_beam* beams, int64_t nbm, c
   else if (!(p->n_in > 0) || !(p->n_out > 0)) e << "refractive indices must be positive";
   else if (!p->fc_Q || !p->fc_A) e << "fc_Q and fc_A tables are required";
   else if (p->ckpt_every < 0) e << "ckpt_every must be >= 0";
+  else if (p->combo_chunk < 0) e << "combo_chunk must be >= 0";
   else if (nbm < 0 || (nbm > 0 && !beams)) e << "bad beam array";
   else if (nd < 0 || (nd > 0 && !dets)) e << "bad detector array";
   if (e.str().empty()) {
@@ -268,6 +269,9 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
   int maxg = 0;
   for (int64_t k = 0; k < n_beams; ++k) maxg = std::max(maxg, beams[k].group);
   p.Nq = maxg + 1;
+  p.chunk = (prob->combo_chunk > 0) ? std::min<int64_t>(prob->combo_chunk, p.Nq) : p.Nq;
+  p.cq0 = 0;
+  p.cnq = p.chunk;
   const int M = (int)p.M;
   const double dx = (prob->xmax - prob->xmin) / prob->Nx;
   const double dy = (prob->ymax - prob->ymin) / prob->Ny;
@@ -505,7 +509,7 @@ hipError_t prof_begin(Plan& p, int cls, hipStream_t s, hipEvent_t* stop) {
 hipError_t prof_end(hipEvent_t stop, hipStream_t s) { return stop ? hipEventRecord(stop, s) : hipSuccess; }
 
 // ---------------------------------------------------------------- workspace
-int64_t state_elems(const Plan& p) { return p.Nq * p.inst_stride; }
+int64_t state_elems(const Plan& p) { return p.chunk * p.inst_stride; }
 
 static int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 

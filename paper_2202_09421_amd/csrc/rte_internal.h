@@ -96,6 +96,11 @@ struct Plan {
   FcPlanDev fcx{}, fcy{};
   DeviceTables dev;
   int64_t ckpt_every = 0;
+  // combination chunks: the workspace holds `chunk` sources; kernels work on
+  // sources [cq0, cq0 + cnq) of the current chunk (set by the orchestration)
+  int64_t chunk = 1;
+  mutable int64_t cq0 = 0, cnq = 1;
+  int64_t saved_chunk = -1;    // chunk whose forward states are in the workspace
   bool have_forward = false;   // a saved forward lives in the workspace
   int64_t saved_K = 0;
   // graph mode: rte_gradient recorded once per argument set, then replayed

@@ -45,7 +45,7 @@ class rte_problem(ctypes.Structure):
                 ("n_out", ctypes.c_double), ("fc_d", ctypes.c_int64), ("fc_C", ctypes.c_int64),
                 ("filt_alpha", ctypes.c_double), ("filt_beta", ctypes.c_double),
                 ("fc_Q", ctypes.POINTER(ctypes.c_double)), ("fc_A", ctypes.POINTER(ctypes.c_double)),
-                ("ckpt_every", ctypes.c_int64)]
+                ("ckpt_every", ctypes.c_int64), ("combo_chunk", ctypes.c_int64)]
 
 
 class rte_beam(ctypes.Structure):
@@ -122,7 +122,7 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def make_problem(spec, dtype=RTE_F64, ckpt_every=0):
+def make_problem(spec, dtype=RTE_F64, ckpt_every=0, combo_chunk=0):
     """Build the C structs for a problem description (see module docstring)."""
     Q, A = fc_tables(spec.fc_d, spec.fc_C)
     Qc = np.ascontiguousarray(Q, dtype=np.float64)
@@ -138,6 +138,7 @@ def make_problem(spec, dtype=RTE_F64, ckpt_every=0):
     p.fc_Q = Qc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.fc_A = Ac.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.ckpt_every = ckpt_every
+    p.combo_chunk = combo_chunk
     beams = (rte_beam * max(1, len(spec.beams)))()
     for k, b in enumerate(spec.beams):
         beams[k] = rte_beam(b.x, b.y, b.theta, b.sigma_x, b.sigma_theta, b.tau, b.sigma_t, b.t0, b.group, 0)
@@ -150,12 +151,12 @@ def make_problem(spec, dtype=RTE_F64, ckpt_every=0):
 class Plan:
     """A library plan for one problem description (all Nq sources)."""
 
-    def __init__(self, spec, dtype=torch.float64, ckpt_every=0, device=None):
+    def __init__(self, spec, dtype=torch.float64, ckpt_every=0, device=None, combo_chunk=0):
         self.spec = spec
         self.dtype = dtype
         self.device = torch.device("cuda") if device is None else torch.device(device)
         code = RTE_F64 if dtype == torch.float64 else RTE_F32
-        prob, beams, nb, dets, nd, self._keep = make_problem(spec, code, ckpt_every)
+        prob, beams, nb, dets, nd, self._keep = make_problem(spec, code, ckpt_every, combo_chunk)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().rte_plan_create(ctypes.byref(prob), beams, nb, dets, nd, ctypes.byref(h)))
