@@ -238,6 +238,109 @@ def uneven_comparison(scale, log_fn, count=32):
                     "instances above 2 GB of states use checkpoints (one forward replay)" % scale}
 
 
+def full_workload(which, dtype_names, K_override, log_fn, plain=True):
+    """Full-size runs of the large workloads with checkpointed replay: the
+    8-combination MSS problem (513 x 513 nodes, 64 ordinates, 6000 steps) or
+    the neck phantom (1025 x 1025 nodes, 64 ordinates, 4 combinations, 6000
+    steps, a checkpoint every 200 steps).
+
+    "batched": chunks of as many combinations as fit in 85 % of free device
+    memory (every launch covers the whole chunk); "plain": one combination per
+    chunk.  MSS: one plan whose gradient call runs every chunk (combo_chunk),
+    so batched and plain gradients must agree bit for bit.  Neck: one plan and
+    one gradient call per chunk (each call stays near a minute), gradients
+    summed on the host, so the two sums agree to rounding only."""
+    import dataclasses
+    import math
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2202_09421_amd import rte
+
+    full = W.config(2) if which == "mss-full" else W.neck_phantom()
+    spec = full.with_(K=K_override) if K_override else full
+    ckpt = 200 if which == "neck" else max(8, int(round(math.sqrt(4 * spec.K))))
+    ckpt = min(ckpt, spec.K)
+    split = which == "neck"
+    ny, nx = spec.Ny + 1, spec.Nx + 1
+    units = nx * ny * spec.M * spec.K * spec.Nq
+
+    def sub_spec(q0, c):
+        beams = [dataclasses.replace(bm, group=bm.group - q0) for bm in spec.beams if q0 <= bm.group < q0 + c]
+        return spec.with_(beams=beams)
+
+    runs = []
+    for dn in dtype_names:
+        tdt = torch.float64 if dn == "f64" else torch.float32
+        a = torch.tensor(spec.mu_a, device="cuda", dtype=tdt)
+        b = torch.tensor(spec.mu_s, device="cuda", dtype=tdt)
+        free = torch.cuda.mem_get_info()[0]
+        chunk = spec.Nq
+        while True:
+            probe = rte.Plan(sub_spec(0, chunk) if split else spec, tdt, ckpt_every=ckpt, combo_chunk=chunk)
+            need = probe.workspace_bytes(True)
+            probe.close()
+            if need <= 0.85 * free or chunk == 1:
+                break
+            chunk -= 1
+        n_chunks = -(-spec.Nq // chunk)
+        chunk = -(-spec.Nq // n_chunks)   # same number of chunks, sizes as even as possible
+        if need > 0.85 * free:
+            raise RuntimeError("%s %s: one combination needs %.1f GB, %.1f GB free" % (which, dn, need / 1e9, free / 1e9))
+        res = {"dtype": dn, "ckpt_every": ckpt}
+        grads = {}
+        for label, c in (("batched", chunk), ("plain", 1)):
+            if label == "plain" and (not plain or chunk == 1):
+                continue
+            pieces = [(q0, min(c, spec.Nq - q0)) for q0 in range(0, spec.Nq, c)] if split else [(0, spec.Nq)]
+            total, J_sum, ga_sum, gb_sum, ws_gb = 0.0, 0.0, None, None, 0.0
+            for q0, cq in pieces:
+                sp = sub_spec(q0, cq) if split else spec
+                plan = rte.Plan(sp, tdt, ckpt_every=ckpt, combo_chunk=cq if split else c)
+                sched = plan.autotune(a, b, cache=False)
+                ws_gb = max(ws_gb, plan.workspace_bytes(True) / 1e9)
+                log_fn("bench: %s %s %s: combinations %d..%d, combo_chunk %d, workspace %.1f GB, schedule %s" % (
+                    which, dn, label, q0, q0 + cq - 1, cq if split else c, ws_gb,
+                    {k: v for k, v in sched.items() if k != "cached"}))
+                gm = torch.zeros((plan.Nq, plan.Nd, spec.K), device="cuda", dtype=torch.float64)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                J, ga, gb, G = plan.gradient(a, b, gm)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if not np.isfinite(float(J.item())) or not torch.isfinite(ga).all():
+                    raise RuntimeError("non-finite gradient")
+                total += dt
+                J_sum += float(J.item())
+                ga_sum = ga.clone() if ga_sum is None else ga_sum + ga
+                gb_sum = gb.clone() if gb_sum is None else gb_sum + gb
+                log_fn("bench: %s %s %s: gradient call %.2f s (J = %.6e)" % (which, dn, label, dt, float(J.item())))
+                plan.close()
+                del plan, J, ga, gb, G, gm
+                torch.cuda.empty_cache()
+            log_fn("bench: %s %s %s gradient: %.2f s, %.3e units/s (J = %.6e)" % (which, dn, label, total,
+                                                                                  units / total, J_sum))
+            res[label] = {"combo_chunk": c, "calls": len(pieces), "seconds": total, "value": units / total,
+                          "J": J_sum, "workspace_GB": ws_gb, "schedule": {k: v for k, v in sched.items() if k != "cached"}}
+            grads[label] = (ga_sum, gb_sum)
+        if "plain" in res:
+            rel = lambda x, y: float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y))
+            res["batched_over_plain"] = res["batched"]["value"] / res["plain"]["value"]
+            res["gradients_bitwise_equal"] = all(bool(torch.equal(x, y)) for x, y in zip(grads["batched"], grads["plain"]))
+            res["gradients_max_rel_diff"] = max(rel(x, y) for x, y in zip(grads["batched"], grads["plain"]))
+        runs.append(res)
+        del grads
+        torch.cuda.empty_cache()
+    return {"workload": full.name, "grid": "%dx%d" % (nx, ny), "ordinates": spec.M, "combinations": spec.Nq,
+            "detectors": len(spec.detectors), "time_steps": spec.K, "time_steps_full": full.K,
+            "unit": "cell*ordinate*steps/s", "units_per_gradient": units,
+            "launch": "eager (one stream); checkpoints every ckpt_every steps, segments replayed in the adjoint; "
+                      + ("one gradient call per chunk of combinations" if split else "one gradient call (all chunks)"),
+            "runs": runs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +361,12 @@ def main():
                     help="one eager gradient only (no graph, no events): the command profiled for counters")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized tensor 5 times (calibrates the HBM byte counters)")
+    ap.add_argument("--workload", choices=["gradient", "mss-full", "neck"], default="gradient",
+                    help="gradient (default): the benchmark line; mss-full / neck: one full-size gradient of the "
+                         "MSS or neck-phantom workload, batched and plain (prints its own JSON line)")
+    ap.add_argument("--workload-steps", type=int, default=0,
+                    help="with --workload mss-full/neck: run only the first K steps (0 = all)")
+    ap.add_argument("--no-plain", action="store_true", help="with --workload mss-full/neck: skip the plain run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
@@ -279,6 +388,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("bench: copied %d MiB x 5" % args.copy_calibration)
+        return
+    if args.workload != "gradient":
+        dts = ["f64", "f32"] if args.workload == "mss-full" else ["f32"]
+        out = full_workload(args.workload, dts, args.workload_steps, log, plain=not args.no_plain)
+        print(json.dumps(out), flush=True)
         return
     spec = W.config(1)
     tdt = torch.float64 if args.dtype == "f64" else torch.float32

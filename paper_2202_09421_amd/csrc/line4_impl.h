@@ -55,6 +55,10 @@ __device__ __forceinline__ int remap_unit16(int b) {
   return chunk * 16 + 2 * x + h;
 }
 constexpr size_t kLines4MaxLds = 64 * 1024;
+// Extended lengths above kLongLine (up to 40 x 40): the line buffer alone
+// takes up to 80 KB, so the continuation matrix is read from global memory
+// (L1 / L2) instead of LDS, and the LDS cap is raised (gfx950: 160 KB per CU).
+constexpr size_t kLines4MaxLdsLong = 96 * 1024;
 
 // thread-owned loads of one unit: point i of line it (0/1) for
 // e = tid + NTH t, i = e / 2, it = e % 2; 4 slots each
@@ -327,10 +331,11 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
 }
 
 // Issue the loads of the FC tables into registers (kept until staged).
-template <int N, int NTH, bool TG>
+// MXG: the continuation matrix stays in global memory (long lines).
+template <int N, int NTH, bool TG, bool MXG>
 struct TabRegs {
   static constexpr int RT = TG ? 1 : (N + NTH - 1) / NTH, MT = TG ? 1 : (N + NTH - 1) / NTH,
-                       XT = (kFcTab + NTH - 1) / NTH;
+                       XT = MXG ? 1 : (kFcTab + NTH - 1) / NTH;
   double rr[RT][2], mm[MT], xx[XT];
   __device__ __forceinline__ void load(const FcPlanDev& fc, int lane) {
     const int nmx = 2 * fc.d * (fc.C + fc.E);
@@ -347,10 +352,12 @@ struct TabRegs {
         mm[t] = (k < N) ? fc.mu[k] : 0.0;
       }
     }
+    if (!MXG) {
 #pragma unroll
-    for (int t = 0; t < XT; ++t) {
-      const int k = lane + NTH * t;
-      xx[t] = (k < nmx) ? fc.Mx[k] : 0.0;
+      for (int t = 0; t < XT; ++t) {
+        const int k = lane + NTH * t;
+        xx[t] = (k < nmx) ? fc.Mx[k] : 0.0;
+      }
     }
   }
   __device__ __forceinline__ void stage(cx<double>* roots, double* mu, double* Mx, int nmx, int lane) const {
@@ -366,10 +373,12 @@ struct TabRegs {
         if (k < N) mu[k] = mm[t];
       }
     }
+    if (!MXG) {
 #pragma unroll
-    for (int t = 0; t < XT; ++t) {
-      const int k = lane + NTH * t;
-      if (k < nmx) Mx[k] = xx[t];
+      for (int t = 0; t < XT; ++t) {
+        const int k = lane + NTH * t;
+        if (k < nmx) Mx[k] = xx[t];
+      }
     }
   }
 };
@@ -384,6 +393,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
   constexpr int N = N1 * N2;
   constexpr int NTH = 64 * NW;
   constexpr int TMAX = (2 * N + NTH - 1) / NTH;
+  constexpr bool MXG = N > kLongLine;
   typedef L4Smem<N1, N2> SM;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sm = reinterpret_cast<double*>(smem_raw);
@@ -391,7 +401,8 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
   cx<double>* fold = reinterpret_cast<cx<double>*>(sm + SM::BUF);
   cx<double>* roots = reinterpret_cast<cx<double>*>(sm + SM::BUF + SM::FOLD);
   double* mu = sm + SM::BUF + SM::FOLD + SM::ROOTS;
-  double* Mx = sm + SM::mx_off(TG);
+  double* MxS = sm + SM::mx_off(TG);            // staged copy (unused when MXG)
+  const double* Mx = MXG ? a.fc.Mx : MxS;
 
   const FcPlanDev& fc = a.fc;
   const int n = fc.n, dd = fc.d, CE = fc.C + fc.E;
@@ -403,9 +414,9 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
     UnitRegs<T, TMAX> R0, R1;
     load_unit<T, TMAX, NTH>(a, d0, n, tid, R0);
     load_unit<T, TMAX, NTH>(a, d1, n, tid, R1);
-    TabRegs<N, NTH, TG> tab;
+    TabRegs<N, NTH, TG, MXG> tab;
     tab.load(fc, tid);
-    tab.stage(roots, mu, Mx, 2 * dd * CE, tid);
+    tab.stage(roots, mu, MxS, 2 * dd * CE, tid);
     if (d0.live) {
       stage_unit<T, TMAX, N1, N2, NTH>(R0, d0, a.coef[d0.dir], ADJ, n, tid, buf);
       __syncthreads();
@@ -421,9 +432,9 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
     const UnitDesc d0 = decode_unit(a, remap_unit16((int)blockIdx.x));
     if (!d0.live) return;
     {
-      TabRegs<N, NTH, TG> tab;
+      TabRegs<N, NTH, TG, MXG> tab;
       tab.load(fc, tid);
-      tab.stage(roots, mu, Mx, 2 * dd * CE, tid);
+      tab.stage(roots, mu, MxS, 2 * dd * CE, tid);
     }
     constexpr int CH = 8;
     for (int c0 = 0; c0 < TMAX; c0 += CH) {
@@ -518,5 +529,23 @@ hipError_t lines4_extra2(const Lines4Args<double>& a, bool adj, hipStream_t s);
 hipError_t lines4_extra2(const Lines4Args<float>& a, bool adj, hipStream_t s);
 hipError_t lines4_extra3(const Lines4Args<double>& a, bool adj, hipStream_t s);
 hipError_t lines4_extra3(const Lines4Args<float>& a, bool adj, hipStream_t s);
+
+// Extended lengths above kLongLine: one unit per two-wave workgroup, twiddles,
+// multipliers and continuation matrix from global memory (line4_long*.hip).
+template <typename T, bool ADJ, int N1, int N2>
+inline hipError_t go_long(const Lines4Args<T>& a, hipStream_t s) {
+  static_assert(N1 * N2 > kLongLine, "long-line variant");
+  const size_t sh = L4Smem<N1, N2>::bytes(0, true);
+  if (sh > kLines4MaxLdsLong) return hipErrorNotSupported;
+  if (a.nunits == 0) return hipSuccess;
+  const int groups = ((a.nunits + 15) / 16) * 16;
+  hipLaunchKernelGGL((lines4_kernel<T, ADJ, N1, N2, 1, 2, true>), dim3((unsigned)groups), dim3(128), sh, s, a);
+  return hipGetLastError();
+}
+
+hipError_t lines4_long0(const Lines4Args<double>& a, bool adj, hipStream_t s);
+hipError_t lines4_long0(const Lines4Args<float>& a, bool adj, hipStream_t s);
+hipError_t lines4_long1(const Lines4Args<double>& a, bool adj, hipStream_t s);
+hipError_t lines4_long1(const Lines4Args<float>& a, bool adj, hipStream_t s);
 
 }  // namespace rte

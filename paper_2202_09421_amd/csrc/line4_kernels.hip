@@ -4,8 +4,9 @@
 
 namespace rte {
 
-// N_p = N1 x N2 with both factors products of 2, 3, 4, 5 (register codelets)
-// and at most 32 (one pass over the lanes of a two-wave workgroup).
+// N_p = N1 x N2 with both factors products of 2, 3, 4, 5 (register codelets):
+// up to 600 both at most 32 (one pass over the lanes of a two-wave
+// workgroup); above, N1 <= 32 and N2 <= 40.
 bool fourstep_split(int Np, int* n1, int* n2) {
   switch (Np) {
     case 45: *n1 = 5; *n2 = 9; return true;
@@ -58,6 +59,26 @@ bool fourstep_split(int Np, int* n1, int* n2) {
     case 540: *n1 = 20; *n2 = 27; return true;
     case 576: *n1 = 24; *n2 = 24; return true;
     case 600: *n1 = 24; *n2 = 25; return true;
+    // above 600: both factors at most 40 (long-line variant)
+    case 625: *n1 = 25; *n2 = 25; return true;
+    case 640: *n1 = 32; *n2 = 20; return true;
+    case 648: *n1 = 27; *n2 = 24; return true;
+    case 675: *n1 = 27; *n2 = 25; return true;
+    case 720: *n1 = 30; *n2 = 24; return true;
+    case 729: *n1 = 27; *n2 = 27; return true;
+    case 750: *n1 = 30; *n2 = 25; return true;
+    case 768: *n1 = 32; *n2 = 24; return true;
+    case 800: *n1 = 32; *n2 = 25; return true;
+    case 810: *n1 = 30; *n2 = 27; return true;
+    case 864: *n1 = 32; *n2 = 27; return true;
+    case 900: *n1 = 30; *n2 = 30; return true;
+    case 960: *n1 = 32; *n2 = 30; return true;
+    case 972: *n1 = 27; *n2 = 36; return true;
+    case 1000: *n1 = 25; *n2 = 40; return true;
+    case 1024: *n1 = 32; *n2 = 32; return true;
+    case 1080: *n1 = 30; *n2 = 36; return true;
+    case 1152: *n1 = 32; *n2 = 36; return true;
+    case 1200: *n1 = 30; *n2 = 40; return true;
     default: return false;
   }
 }
@@ -80,6 +101,8 @@ static hipError_t by_size(const Lines4Args<T>& a, int upw, int nw, int tg, hipSt
       if (e == hipErrorNotSupported) e = lines4_extra1(a, ADJ, s);
       if (e == hipErrorNotSupported) e = lines4_extra2(a, ADJ, s);
       if (e == hipErrorNotSupported) e = lines4_extra3(a, ADJ, s);
+      if (e == hipErrorNotSupported) e = lines4_long0(a, ADJ, s);
+      if (e == hipErrorNotSupported) e = lines4_long1(a, ADJ, s);
       return e;
     }
   }

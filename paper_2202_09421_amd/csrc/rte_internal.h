@@ -16,6 +16,7 @@ constexpr int kMaxPasses = 12;   // FFT passes (radices 2,3,4,5)
 constexpr int kMaxFcD = 8;       // matching points supported
 constexpr int kLineThreads = 128; // generic (Stockham) line kernel
 constexpr int kFcTab = 384;      // continuation matrix entries ((C+E) * 2d) staged by the four-step kernel
+constexpr int kLongLine = 600;   // four-step lengths above this read the continuation matrix from global memory
 
 void set_error(const std::string& msg);
 const char* last_error();

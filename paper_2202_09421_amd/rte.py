@@ -169,9 +169,13 @@ class Plan:
         self._gout = None
 
     def close(self):
+        """Destroy the library plan and drop the workspace and output buffers
+        (their memory returns to torch's allocator)."""
         if getattr(self, "_h", None):
             lib().rte_plan_destroy(self._h)
             self._h = None
+        self._ws = None
+        self._gout = None
 
     def __del__(self):
         try:

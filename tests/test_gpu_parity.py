@@ -96,8 +96,10 @@ CASES = [
     dict(N=12, M=80, K=6, seed=10, n_in=1.33),              # 5 row tiles (runtime tile count)
     dict(N=64, M=16, K=10, seed=11, Ny=20, n_in=1.4),       # four-step x lines, generic y lines
     dict(N=128, M=8, K=6, seed=12, n_in=1.4),               # N_p = 160 (16 x 10 split)
+    dict(N=1024, M=4, K=6, seed=13, Ny=9, n_in=1.4),        # x lines N_p = 1080 (generic kernel)
+    dict(N=9, M=8, K=6, seed=14, Ny=700, n_in=1.33),        # y lines N_p = 729 = 3^6 (generic)
 ]
-GRAD_CASES = [0, 1, 2, 3, 4, 5, 7, 8, 9, 10]
+GRAD_CASES = [0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 12, 13]
 
 
 def _spec(case):
@@ -258,3 +260,24 @@ def test_gradient_workload_full_size_spot_checks(rte):
     eps = 1e-4
     fd = (Jat(eps) - Jat(-eps)) / (2 * eps)
     assert abs(fd - ad) < 1e-6 * abs(ad), (fd, ad)
+
+
+def test_neck_phantom_first_steps(rte):
+    # the neck phantom's own grid (1025 x 1025 nodes, 64 ordinates: x and y
+    # lines of N_p = 1080 on the generic line kernel), one combination, the
+    # first 3 steps, FP64 and FP32 against the FP64 oracle
+    import dataclasses
+    full = W.neck_phantom()
+    spec = full.with_(K=3, beams=[dataclasses.replace(b, group=0) for b in full.beams if b.group == 0])
+    say("neck first steps", spec.Nx + 1, spec.M, spec.K)
+    G_o, uK_o, _ = Oracle(spec).forward()
+    scale = max(np.abs(G_o).max(), np.abs(uK_o).max())
+    for dt, bar in ((torch.float64, TOL64), (torch.float32, TOL32)):
+        plan = rte.Plan(spec, dt)
+        assert plan.Np_x == 1080 and plan.Np_y == 1080
+        G, uK = plan.forward(spec.mu_a, spec.mu_s, want_u_final=True)
+        torch.cuda.synchronize()
+        eu, eg = rel(uK.cpu(), uK_o), np.abs(G.cpu().numpy() - G_o).max() / scale
+        say("  %s: u %.2e  G (max abs / state max) %.2e" % (dt, eu, eg))
+        assert eu < bar and eg < bar
+        plan.close()
