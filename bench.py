@@ -175,8 +175,8 @@ def mss_comparison(K, dtype_name, log_fn):
     rel = lambda x, y: float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y))
     return {"workload": full.name, "grid": "%dx%d" % (nx, ny), "ordinates": spec.M, "combinations": nq,
             "time_steps": K, "time_steps_full": full.K, "dtype": dtype_name,
-            "sample": "first %d of %d steps, every state kept (the full run needs checkpoints and %s)" % (
-                K, full.K, "two-level storage in FP64" if dtype_name == "f64" else "one-level checkpoints"),
+            "sample": "first %d of %d steps, every state kept (the full-length run, with checkpoints and "
+                      "combination chunks, is bench.py --workload mss-full)" % (K, full.K),
             "batched_value": res["batched"], "plain_value": res["plain"],
             "unit": "cell*ordinate*steps/s", "batched_over_plain": res["batched"] / res["plain"],
             "plain_vs_batched_gradient_rel_diff": max(rel(ga_sum, gab), rel(gb_sum, gbb))}

@@ -122,9 +122,11 @@ __device__ __forceinline__ void load_unit(const Lines4Args<T>& a, const UnitDesc
 
 // LDS layout (doubles): buf [kLP][LSZ] complex (rows of N2 + 1 entries, line
 // stride LSZ = 2 mod 4 entries so that the two lines stored by neighbouring
-// lanes fall in different bank halves) | fold [kLP][2 kMaxFcD] complex |
-// roots, complex, entry e at e + e / 16 (spreads the strided twiddle reads
-// over the banks) | mu [N] | continuation matrix [(C+E) x 2d]
+// lanes fall in different bank halves) | roots, complex, entry e at e + e / 16
+// (spreads the strided twiddle reads over the banks) | mu [N] | continuation
+// matrix [(C+E) x 2d].  The transpose keeps its 2d fold values per line in
+// the line's own extension region (positions n .. n + 2d - 1, free once the
+// fold sums are formed; C + E >= 2d is checked by the plan).
 template <int N1, int N2>
 struct L4Smem {
   static constexpr int N = N1 * N2;
@@ -133,15 +135,24 @@ struct L4Smem {
   static constexpr int LSZ = LSZ0 + (6 - LSZ0 % 4) % 4;
   static constexpr int NR = N + N / 16 + 1;
   static constexpr int BUF = 2 * kLP * LSZ;
-  static constexpr int FOLD = 2 * kLP * 2 * kMaxFcD;
   static constexpr int ROOTS = 2 * NR;
   static constexpr int MU = N;
-  static constexpr int FIXED = BUF + FOLD + ROOTS + MU;
-  // nmx = (C + E) * 2d continuation entries; TG: twiddles and multipliers
-  // are read from global memory (L1 / L2) instead of being staged
-  static constexpr int mx_off(bool tg) { return BUF + FOLD + (tg ? 0 : ROOTS + MU); }
+  // nmx = (C + E) * 2d continuation entries staged (0 when read from global
+  // memory); TG: twiddles and multipliers are read from global memory (L1 /
+  // L2) instead of being staged
+  static constexpr int mx_off(bool tg) { return BUF + (tg ? 0 : ROOTS + MU); }
   static constexpr size_t bytes(int nmx, bool tg) { return sizeof(double) * (size_t)(mx_off(tg) + nmx); }
 };
+
+// The transpose (ADJ) and the long lines read the continuation matrix from
+// global memory; the forward pass of lengths up to kLongLine stages it.
+template <bool ADJ, int N>
+constexpr bool kMxGlobal = ADJ || N > kLongLine;
+
+template <bool ADJ, int N1, int N2, bool TG>
+inline size_t l4_lds_bytes(const FcPlanDev& fc) {
+  return L4Smem<N1, N2>::bytes(kMxGlobal<ADJ, N1 * N2> ? 0 : 2 * fc.d * (fc.C + fc.E), TG);
+}
 
 __device__ __forceinline__ int rix(int e) { return e + (e >> 4); }
 
@@ -170,23 +181,10 @@ __device__ __forceinline__ void stage_unit(const UnitRegs<T, TMAX>& R, const Uni
   }
 }
 
-// Store one complex point of complex line l (line l / 2 of the pair, slots
-// 2 (l % 2) and 2 (l % 2) + 1), scaled by (c0, c1).
-template <typename T>
-__device__ __forceinline__ void store_pt(T* out, int64_t ls, int64_t ps, int l, int p, double re, double im, double c0,
-                                         double c1) {
-  T* q = out + (l >> 1) * ls + (int64_t)p * ps + 2 * (l & 1);
-  if constexpr (sizeof(T) == 8) {
-    *reinterpret_cast<double2*>(q) = make_double2(c0 * re, c1 * im);
-  } else {
-    *reinterpret_cast<float2*>(q) = make_float2(float(c0 * re), float(c1 * im));
-  }
-}
-
 // Continuation, derivative (or its transpose) and store of one staged unit.
 template <typename T, bool ADJ, int N1, int N2, int NTH, bool TG>
 __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int dd, int CE,
-                                               int tid, cx<double>* buf, cx<double>* fold, const cx<double>* roots,
+                                               int tid, cx<double>* buf, const cx<double>* roots,
                                                const double* mu, const double* Mx) {
   const double* __restrict__ groots = a.fc.roots;
   const double* __restrict__ gmu = a.fc.mu;
@@ -277,10 +275,13 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
 
   if (ADJ) {
     // fold the extension region back onto the 2d matching points (transpose
-    // of the continuation): column c of the continuation matrix
-    for (int t = tid; t < kLP * 2 * dd; t += NTH) {
-      const int l = t / (2 * dd), c = t % (2 * dd);
-      double sr = 0.0, si = 0.0;
+    // of the continuation): thread t < kLP 2d forms column c of line l, and
+    // after every thread has read the region stores it at position n + c
+    static_assert(kLP * 2 * kMaxFcD <= NTH, "one fold column per thread");
+    const bool act = tid < kLP * 2 * dd;
+    const int l = tid / (2 * dd), c = tid % (2 * dd);
+    double sr = 0.0, si = 0.0;
+    if (act) {
 #pragma unroll 4
       for (int p = 0; p < CE; ++p) {
         const double mv = Mx[p * 2 * dd + c];
@@ -288,8 +289,9 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
         sr += mv * y.re;
         si += mv * y.im;
       }
-      fold[l * 2 * kMaxFcD + c] = {sr, si};
     }
+    __syncthreads();
+    if (act) buf[l * LSZ + ph(n + c)] = {sr, si};
     __syncthreads();
   }
 
@@ -308,13 +310,13 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
       double dv[4] = {z0.re, z0.im, z1.re, z1.im};
       if (ADJ) {
         if (i >= n - dd) {
-          const cx<double> f0 = fold[(2 * it) * 2 * kMaxFcD + (i - (n - dd))];
-          const cx<double> f1 = fold[(2 * it + 1) * 2 * kMaxFcD + (i - (n - dd))];
+          const int fp = ph(n + (i - (n - dd)));
+          const cx<double> f0 = buf[(2 * it) * LSZ + fp], f1 = buf[(2 * it + 1) * LSZ + fp];
           dv[0] += f0.re; dv[1] += f0.im; dv[2] += f1.re; dv[3] += f1.im;
         }
         if (i < dd) {
-          const cx<double> f0 = fold[(2 * it) * 2 * kMaxFcD + dd + (dd - 1 - i)];
-          const cx<double> f1 = fold[(2 * it + 1) * 2 * kMaxFcD + dd + (dd - 1 - i)];
+          const int fp = ph(n + dd + (dd - 1 - i));
+          const cx<double> f0 = buf[(2 * it) * LSZ + fp], f1 = buf[(2 * it + 1) * LSZ + fp];
           dv[0] += f0.re; dv[1] += f0.im; dv[2] += f1.re; dv[3] += f1.im;
         }
       }
@@ -393,14 +395,13 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
   constexpr int N = N1 * N2;
   constexpr int NTH = 64 * NW;
   constexpr int TMAX = (2 * N + NTH - 1) / NTH;
-  constexpr bool MXG = N > kLongLine;
+  constexpr bool MXG = kMxGlobal<ADJ, N>;
   typedef L4Smem<N1, N2> SM;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sm = reinterpret_cast<double*>(smem_raw);
   cx<double>* buf = reinterpret_cast<cx<double>*>(sm);
-  cx<double>* fold = reinterpret_cast<cx<double>*>(sm + SM::BUF);
-  cx<double>* roots = reinterpret_cast<cx<double>*>(sm + SM::BUF + SM::FOLD);
-  double* mu = sm + SM::BUF + SM::FOLD + SM::ROOTS;
+  cx<double>* roots = reinterpret_cast<cx<double>*>(sm + SM::BUF);
+  double* mu = sm + SM::BUF + SM::ROOTS;
   double* MxS = sm + SM::mx_off(TG);            // staged copy (unused when MXG)
   const double* Mx = MXG ? a.fc.Mx : MxS;
 
@@ -420,13 +421,13 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
     if (d0.live) {
       stage_unit<T, TMAX, N1, N2, NTH>(R0, d0, a.coef[d0.dir], ADJ, n, tid, buf);
       __syncthreads();
-      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, fold, roots, mu, Mx);
+      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, roots, mu, Mx);
     }
     if (d1.live) {
       __syncthreads();
       stage_unit<T, TMAX, N1, N2, NTH>(R1, d1, a.coef[d1.dir], ADJ, n, tid, buf);
       __syncthreads();
-      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d1, n, dd, CE, tid, buf, fold, roots, mu, Mx);
+      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d1, n, dd, CE, tid, buf, roots, mu, Mx);
     }
   } else {
     const UnitDesc d0 = decode_unit(a, remap_unit16((int)blockIdx.x));
@@ -480,7 +481,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
       }
     }
     __syncthreads();
-    transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, fold, roots, mu, Mx);
+    transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, roots, mu, Mx);
   }
 }
 
@@ -490,7 +491,7 @@ constexpr bool kPairOk = (2 * N1 * N2 + 64 * NW - 1) / (64 * NW) <= 9;
 
 template <typename T, bool ADJ, int N1, int N2, int NW, bool TG>
 inline hipError_t go_nw(const Lines4Args<T>& a, int upw, hipStream_t s) {
-  const size_t sh = L4Smem<N1, N2>::bytes(2 * a.fc.d * (a.fc.C + a.fc.E), TG);
+  const size_t sh = l4_lds_bytes<ADJ, N1, N2, TG>(a.fc);
   if (sh > kLines4MaxLds) return hipErrorNotSupported;
   if constexpr (kPairOk<N1, N2, NW>) {
     if (upw == 2) {
@@ -510,7 +511,7 @@ inline hipError_t go_nw(const Lines4Args<T>& a, int upw, hipStream_t s) {
 // variant instantiated for the lengths outside the fully tuned set.
 template <typename T, bool ADJ, int N1, int N2>
 inline hipError_t go_one(const Lines4Args<T>& a, hipStream_t s) {
-  const size_t sh = L4Smem<N1, N2>::bytes(2 * a.fc.d * (a.fc.C + a.fc.E), true);
+  const size_t sh = l4_lds_bytes<ADJ, N1, N2, true>(a.fc);
   if (sh > kLines4MaxLds) return hipErrorNotSupported;
   if (a.nunits == 0) return hipSuccess;
   const int groups = ((a.nunits + 15) / 16) * 16;
@@ -535,7 +536,7 @@ hipError_t lines4_extra3(const Lines4Args<float>& a, bool adj, hipStream_t s);
 template <typename T, bool ADJ, int N1, int N2>
 inline hipError_t go_long(const Lines4Args<T>& a, hipStream_t s) {
   static_assert(N1 * N2 > kLongLine, "long-line variant");
-  const size_t sh = L4Smem<N1, N2>::bytes(0, true);
+  const size_t sh = l4_lds_bytes<ADJ, N1, N2, true>(a.fc);
   if (sh > kLines4MaxLdsLong) return hipErrorNotSupported;
   if (a.nunits == 0) return hipSuccess;
   const int groups = ((a.nunits + 15) / 16) * 16;

@@ -176,8 +176,9 @@ static bool build_fc(const rte_problem& pb, int n, double h, std::vector<double>
         buf.push_back((double)acc);
       }
   }
-  // lengths up to kLongLine stage the (C+E) x 2d continuation matrix in LDS
-  if (!fourstep_split(Np, &fc.n1, &fc.n2) || CE > 64 || (Np <= kLongLine && 2 * d * CE > kFcTab))
+  // lengths up to kLongLine stage the (C+E) x 2d continuation matrix in LDS;
+  // the transpose keeps its 2d fold values in the C+E extension positions
+  if (!fourstep_split(Np, &fc.n1, &fc.n2) || CE > 64 || CE < 2 * d || (Np <= kLongLine && 2 * d * CE > kFcTab))
     fc.n1 = fc.n2 = 0;
   return true;
 }
