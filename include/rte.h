@@ -147,6 +147,25 @@ int rte_gradient(rte_plan* plan, const void* mu_a, const void* mu_s, const doubl
                  double* J, double* dmu_a, double* dmu_s, double* G, void* workspace,
                  int64_t workspace_bytes, void* stream);
 
+/* The paper's own gradient (Sec. 3.3): the continuous adjoint problem
+ * eq. (AdjointProblem) solved by the forward machinery, then eq. (FDwin22).
+ * With s = T - t and reversed ordinates, psi(x, theta, s) = lambda(x,
+ * theta + pi, T - s) satisfies the forward equation with zero initial data;
+ * its inflow condition is the forward one (Fresnel reflection) plus the
+ * detector residual (1 - f) sum_j (G_j - G~_j) w(|x - x_j| / sigma_d) at
+ * t = T - s.  Each psi step is a forward step (line pass, node pass), and
+ * the node pass adds, with psi^k = lambda(t_{K-k}) paired with u^{K-k},
+ *   dmu_a -= dtheta dx dy dt sum_m lambda_m u_m,
+ *   dmu_s += dtheta dx dy dt sum_m lambda_m ((W u)_m - u_m).
+ * Same arguments, outputs and workspace as rte_gradient (J and G identical
+ * to it); the gradient approximates the exact discrete one of rte_gradient
+ * to discretisation error (first order under refinement), not to rounding.
+ * Always launched eagerly (graph mode does not apply).  Leaves the forward
+ * states in the workspace like rte_gradient.                              */
+int rte_gradient_continuous(rte_plan* plan, const void* mu_a, const void* mu_s, const double* G_meas,
+                            double* J, double* dmu_a, double* dmu_s, double* G, void* workspace,
+                            int64_t workspace_bytes, void* stream);
+
 /* Graph mode.  With enable != 0, rte_gradient records its whole launch
  * sequence (forward, misfit, adjoint: ~6 kernels per time step) into one HIP
  * graph on first use and replays it while the argument pointers and the

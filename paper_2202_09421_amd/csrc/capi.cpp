@@ -247,6 +247,90 @@ int run_adjoint(Plan& p, const void* mu_a, const void* mu_s, const double* Gbar,
   return RTE_OK;
 }
 
+// ---------------------------------------------------------------- continuous adjoint
+// psi(x, theta, s) = lambda(x, theta + pi, T - s) solves the forward equation
+// (eq. AdjointProblem in reversed time and ordinates), so each of its steps is
+// a forward step whose node pass takes the detector residual as inflow source
+// and adds the eq. (FDwin22) terms.  Its arrays: without checkpoints no
+// forward step runs meanwhile and the forward work arrays are free; with
+// checkpoints the segment replays use them and psi takes the adjoint arrays.
+struct PsiArrays {
+  void* psi[2];
+  void* lr[3];
+  void* X;
+  void* Y;
+};
+
+PsiArrays psi_arrays(const Plan& p, const Workspace& ws) {
+  if (p.ckpt_every == 0) return {{ws.vring[3], ws.ap1}, {ws.lring[0], ws.lring[1], ws.lring[2]}, ws.tx, ws.ty};
+  return {{ws.vring[0], ws.vring[1]}, {ws.vring[2], ws.vring[3], ws.ap1}, ws.atx, ws.aty};
+}
+
+// psi^k -> psi^{k+1}; upair = u^{K-k} (the forward state at the physical time of psi^k)
+int psi_step(Ctx& c, const PsiArrays& A, int k, const void* upair) {
+  const void* in = A.psi[k & 1];
+  LineLaunch ll{in, A.X, A.Y, LINE_FWD, 3};
+  TIMED(RTE_K_LINES_FWD, launch_lines(c.p, ll, c.st));
+  NodeFwdLaunch nf;
+  nf.u = in;
+  nf.X = A.X;
+  nf.Y = A.Y;
+  nf.L1 = A.lr[(k + 2) % 3];
+  nf.L2 = A.lr[(k + 1) % 3];
+  nf.L3 = A.lr[k % 3];
+  nf.mu_a = c.mu_a;
+  nf.mu_s = c.mu_s;
+  nf.u_out = A.psi[(k + 1) & 1];
+  nf.L_out = A.lr[k % 3];
+  nf.flux = nullptr;
+  nf.step = k;
+  nf.csrc = c.ws.flux;
+  nf.upair = upair;
+  nf.ga = c.ws.ga;
+  nf.gb = c.ws.gb;
+  TIMED(RTE_K_NODE_FWD, launch_node_fwd(c.p, nf, c.st));
+  return RTE_OK;
+}
+
+// The psi time loop of the current chunk (forward states or checkpoints in
+// the workspace, residual source table in ws.flux): psi^0 = 0, zero history.
+int cadj_chunk(Ctx& c) {
+  Plan& p = c.p;
+  Workspace& ws = c.ws;
+  hipStream_t st = c.st;
+  const int64_t S = c.S;
+  const int K = (int)p.K;
+  const PsiArrays A = psi_arrays(p, ws);
+  RTE_CHECK(launch_zero(A.psi[0], S, st));
+  for (int k = 0; k < 3; ++k) RTE_CHECK(launch_zero(A.lr[k], S, st));
+  if (p.ckpt_every == 0) {
+    for (int k = 0; k < K; ++k) {
+      int rc = psi_step(c, A, k, at(ws.states, K - k, S));
+      if (rc != RTE_OK) return rc;
+    }
+    return RTE_OK;
+  }
+  const int s = (int)p.ckpt_every;
+  const int nseg = (K + s - 1) / s;
+  for (int j = nseg - 1; j >= 0; --j) {
+    const int k0 = j * s, k1 = std::min(k0 + s, K);
+    void* ck = at(ws.ckpts, (int64_t)j * 4, S);
+    RTE_CHECK(launch_copy(ws.states, ck, S, st));
+    RTE_CHECK(launch_copy(ws.lring[(k0 + 2) % 3], at(ck, 1, S), S, st));
+    RTE_CHECK(launch_copy(ws.lring[(k0 + 1) % 3], at(ck, 2, S), S, st));
+    RTE_CHECK(launch_copy(ws.lring[k0 % 3], at(ck, 3, S), S, st));
+    for (int k = k0; k < k1; ++k) {
+      int rc = fwd_step(c, k, at(ws.states, k - k0, S), at(ws.states, k + 1 - k0, S), nullptr);
+      if (rc != RTE_OK) return rc;
+    }
+    for (int n = k1; n > k0; --n) {
+      int rc = psi_step(c, A, K - n, at(ws.states, n - k0, S));
+      if (rc != RTE_OK) return rc;
+    }
+  }
+  return RTE_OK;
+}
+
 struct GradArgs {
   const void* mu_a;
   const void* mu_s;
@@ -300,6 +384,46 @@ int enqueue_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
 }
 
 // Graph mode: record the whole sequence once per argument set, then replay.
+// Forward with kept states, misfit, residual source, psi loop with the
+// gradient terms, chunk by chunk: all enqueued on st.
+int enqueue_gradient_continuous(Plan& p, const GradArgs& a, hipStream_t st) {
+  Workspace ws;
+  if (!map_or_fail(p, a.ws, a.wsb, true, &ws)) return RTE_ENOMEM;
+  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
+  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  Ctx c{p, ws, st, a.mu_a, a.mu_s, S};
+  p.have_forward = false;
+  RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
+  const int64_t gbytes = p.Nq * p.nx * p.ny * 8;
+  RTE_CHECK(launch_zero(ws.ga, gbytes, st));
+  RTE_CHECK(launch_zero(ws.gb, gbytes, st));
+  const int64_t nc = n_chunks(p);
+  const int K = (int)p.K;
+  for (int64_t k = 0; k < nc; ++k) {
+    set_chunk(p, k);
+    int rc = forward_chunk(c, true, nullptr);
+    hipError_t e = hipSuccess;
+    if (rc == RTE_OK) e = launch_detect(p, ws.flux, a.G, K, st);
+    if (rc == RTE_OK && e == hipSuccess) e = launch_misfit(p, a.G, a.G_meas, ws.gbar, a.J, K, st);
+    if (rc == RTE_OK && e == hipSuccess) e = launch_cadj_source(p, a.G, a.G_meas, ws.flux, K, st);
+    if (rc == RTE_OK && e != hipSuccess) {
+      set_error(std::string("detector/misfit/source kernel launch failed: ") + hipGetErrorString(e));
+      rc = RTE_EDEVICE;
+    }
+    if (rc == RTE_OK) rc = cadj_chunk(c);
+    if (rc != RTE_OK) {
+      reset_chunk(p);
+      return rc;
+    }
+  }
+  reset_chunk(p);
+  RTE_CHECK(launch_grad_reduce(p, ws.ga, ws.gb, a.dmu_a, a.dmu_s, st));
+  p.have_forward = true;
+  p.saved_chunk = nc - 1;
+  p.saved_K = p.K;
+  return RTE_OK;
+}
+
 int graph_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
   const void* key[9] = {a.mu_a, a.mu_s, a.G_meas, a.J, a.dmu_a, a.dmu_s, a.G, a.ws, nullptr};
   bool same = p.gexec != nullptr && p.gkey_bytes == a.wsb && p.gkey_sched == p.sched_version;
@@ -624,6 +748,24 @@ int rte_gradient(rte_plan* h, const void* mu_a, const void* mu_s, const double* 
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (p.use_graph) return graph_gradient(p, a, st);
     return enqueue_gradient(p, a, st);
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RTE_EINVAL;
+  }
+}
+
+int rte_gradient_continuous(rte_plan* h, const void* mu_a, const void* mu_s, const double* G_meas, double* J,
+                            double* dmu_a, double* dmu_s, double* G, void* workspace, int64_t workspace_bytes,
+                            void* stream) {
+  if (!nonnull(h, "plan") || !nonnull(mu_a, "mu_a") || !nonnull(mu_s, "mu_s") || !nonnull(G_meas, "G_meas") ||
+      !nonnull(J, "J") || !nonnull(dmu_a, "dmu_a") || !nonnull(dmu_s, "dmu_s") || !nonnull(G, "G") ||
+      !nonnull(workspace, "workspace"))
+    return RTE_EINVAL;
+  try {
+    set_error("");
+    Plan& p = *reinterpret_cast<Plan*>(h);
+    GradArgs a{mu_a, mu_s, G_meas, J, dmu_a, dmu_s, G, workspace, workspace_bytes};
+    return enqueue_gradient_continuous(p, a, static_cast<hipStream_t>(stream));
   } catch (const std::exception& e) {
     set_error(e.what());
     return RTE_EINVAL;

@@ -159,13 +159,23 @@ struct NodeFwdArgs {
   T* u_out; T* L_out; double* flux;
   const double* Wt; const BcRule* bc; const double* kappa;
   const double* beam_sp; const double* beam_an; const double* beam_tt; const int32_t* beam_off;
+  // continuous adjoint (CADJ): inflow source table, paired forward state,
+  // reversed-ordinate slots, gradient maps, quadrature dtheta dx dy dt
+  const double* csrc; const T* upair; const int32_t* slot_rev; double* ga; double* gb;
+  double quad;
   NodeGeom geo;
   int step;
   double cdt;
 };
 
 // L_out may alias L3: each element is read and then written by one lane.
-template <typename T, int RTC>
+// CADJ: the same step applied to psi (the adjoint of eq. AdjointProblem in
+// reversed time and ordinates, which satisfies the forward equation): the
+// inflow source is (1 - f) csrc instead of the beams, and the lane adds the
+// eq. (FDwin22) terms of its input psi paired with upair (u at the same
+// physical time, ordinate theta + pi) to the gradient maps:
+//   ga -= quad sum psi u~,  gb += quad sum ((W psi) - psi) u~.
+template <typename T, int RTC, bool CADJ>
 __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwdArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const NodeGeom& G = a.geo;
@@ -183,7 +193,7 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
   const T* L3q = a.L3 + ib;
   T* uoq = a.u_out + ib;
   T* Loq = a.L_out + ib;
-  T u[4], X[4], Y[4], L1[4], L2[4], L3[4];
+  T u[4], X[4], Y[4], L1[4], L2[4], L3[4], up[4];
   uint32_t off[4];
   bool gv[4];
 #pragma unroll
@@ -191,10 +201,16 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
     const int g = 4 * t.rt + v;
     gv[v] = t.valid && g < G.G;
     off[v] = (uint32_t)(((uint32_t)g * (uint32_t)G.grp_stride + (uint32_t)t.P * kGroup + t.r) * sizeof(T));
-    u[v] = X[v] = Y[v] = L1[v] = L2[v] = L3[v] = T(0);
+    u[v] = X[v] = Y[v] = L1[v] = L2[v] = L3[v] = up[v] = T(0);
     if (gv[v]) {
       u[v] = ldo(uq, off[v]); X[v] = ldo(Xq, off[v]); Y[v] = ldo(Yq, off[v]);
       L1[v] = ldo(L1q, off[v]); L2[v] = ldo(L2q, off[v]); L3[v] = ldo(L3q, off[v]);
+      if constexpr (CADJ) {
+        const int sr = a.slot_rev[4 * g + t.r];
+        const uint32_t offr =
+            (uint32_t)(((uint32_t)(sr >> 2) * (uint32_t)G.grp_stride + (uint32_t)t.P * kGroup + (sr & 3)) * sizeof(T));
+        up[v] = ldo(a.upair + ib, offr);
+      }
     }
   }
   const int gn = t.j * G.nx + t.i;
@@ -238,9 +254,15 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
       br[v].flag = 0; br[v].src_a = s; br[v].src_b = s; br[v].pad = 0; br[v].coef_a = 0.0; br[v].coef_b = 0.0;
       if (on) br[v] = a.bc[ty * G.M + s];
       src[v] = T(0);
-      if (on)
-        for (int b = b0; b < b1; ++b)
-          src[v] += T(a.beam_sp[(int64_t)b * G.nb + bp] * a.beam_an[b * G.M + s]) * T(a.beam_tt[(int64_t)b * G.K1 + a.step + 1]);
+      if constexpr (CADJ) {
+        if (on)
+          src[v] = T((1.0 - br[v].coef_a - br[v].coef_b) *
+                     a.csrc[((int64_t)q * G.K1 + a.step + 1) * 4 * G.npos + bp]);
+      } else {
+        if (on)
+          for (int b = b0; b < b1; ++b)
+            src[v] += T(a.beam_sp[(int64_t)b * G.nb + bp] * a.beam_an[b * G.M + s]) * T(a.beam_tt[(int64_t)b * G.K1 + a.step + 1]);
+      }
       k0[v] = (on && a.flux && wl0 >= 0) ? a.kappa[wl0 * G.M + s] : 0.0;
       k1[v] = (on && a.flux && wl1 >= 0) ? a.kappa[wl1 * G.M + s] : 0.0;
     }
@@ -265,6 +287,38 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
 #pragma unroll
   for (int v = 0; v < 4; ++v)
     if (gv[v]) sto(uoq, off[v], un[v]);
+
+  if constexpr (CADJ) {
+    double pa = 0.0, pb = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      pa += (double)u[v] * (double)up[v];
+      pb += ((double)S[v] - (double)u[v]) * (double)up[v];
+    }
+    pa += __shfl_xor(pa, 16);
+    pb += __shfl_xor(pb, 16);
+    pa += __shfl_xor(pa, 32);
+    pb += __shfl_xor(pb, 32);
+    if (G.RT > 1) {
+      if (t.r == 0) {
+        Fx[((t.nt * G.RT + t.rt) * 16 + t.node) * 2 + 0] = pa;
+        Fx[((t.nt * G.RT + t.rt) * 16 + t.node) * 2 + 1] = pb;
+      }
+      __syncthreads();
+      if (t.rt != 0 || t.r != 0 || !t.valid) return;
+      pa = pb = 0.0;
+      for (int k = 0; k < G.RT; ++k) {
+        pa += Fx[((t.nt * G.RT + k) * 16 + t.node) * 2 + 0];
+        pb += Fx[((t.nt * G.RT + k) * 16 + t.node) * 2 + 1];
+      }
+    } else if (t.r != 0 || !t.valid) {
+      return;
+    }
+    const int64_t Nn = (int64_t)G.nx * G.ny;
+    a.ga[(int64_t)q * Nn + gn] -= a.quad * pa;
+    a.gb[(int64_t)q * Nn + gn] += a.quad * pb;
+    return;
+  }
   if (a.flux == nullptr) return;
 
   if (G.RT > 1) {
@@ -480,17 +534,31 @@ static hipError_t node_fwd_t(const Plan& p, const NodeFwdLaunch& L, hipStream_t 
   a.u_out = (T*)L.u_out; a.L_out = (T*)L.L_out; a.flux = L.flux;
   a.Wt = p.dev.Wt; a.bc = p.dev.bc; a.kappa = p.dev.kappa;
   a.beam_sp = p.dev.beam_sp; a.beam_an = p.dev.beam_an; a.beam_tt = p.dev.beam_tt; a.beam_off = p.dev.beam_off;
+  a.csrc = L.csrc; a.upair = (const T*)L.upair; a.slot_rev = p.dev.slot_rev; a.ga = L.ga; a.gb = L.gb;
   a.geo = make_geom(p);
   a.step = L.step;
   a.cdt = p.prob.c * p.prob.dt;
+  a.quad = (2.0 * 3.14159265358979323846 / (double)p.M) * ((p.prob.xmax - p.prob.xmin) / (double)p.prob.Nx) *
+           ((p.prob.ymax - p.prob.ymin) / (double)p.prob.Ny) * p.prob.dt;
   const dim3 grid = node_grid(p, a.geo), block((unsigned)(64 * a.geo.NT * a.geo.RT));
   const size_t sh = node_shmem(a.geo, sizeof(T));
+  if (L.csrc) {
+    if (!L.upair || !L.ga || !L.gb || L.flux) return hipErrorInvalidValue;
+    switch (a.geo.RT) {
+      case 1: hipLaunchKernelGGL((node_fwd_kernel<T, 1, true>), grid, block, sh, s, a); break;
+      case 2: hipLaunchKernelGGL((node_fwd_kernel<T, 2, true>), grid, block, sh, s, a); break;
+      case 3: hipLaunchKernelGGL((node_fwd_kernel<T, 3, true>), grid, block, sh, s, a); break;
+      case 4: hipLaunchKernelGGL((node_fwd_kernel<T, 4, true>), grid, block, sh, s, a); break;
+      default: hipLaunchKernelGGL((node_fwd_kernel<T, 0, true>), grid, block, sh, s, a); break;
+    }
+    return hipGetLastError();
+  }
   switch (a.geo.RT) {
-    case 1: hipLaunchKernelGGL((node_fwd_kernel<T, 1>), grid, block, sh, s, a); break;
-    case 2: hipLaunchKernelGGL((node_fwd_kernel<T, 2>), grid, block, sh, s, a); break;
-    case 3: hipLaunchKernelGGL((node_fwd_kernel<T, 3>), grid, block, sh, s, a); break;
-    case 4: hipLaunchKernelGGL((node_fwd_kernel<T, 4>), grid, block, sh, s, a); break;
-    default: hipLaunchKernelGGL((node_fwd_kernel<T, 0>), grid, block, sh, s, a); break;
+    case 1: hipLaunchKernelGGL((node_fwd_kernel<T, 1, false>), grid, block, sh, s, a); break;
+    case 2: hipLaunchKernelGGL((node_fwd_kernel<T, 2, false>), grid, block, sh, s, a); break;
+    case 3: hipLaunchKernelGGL((node_fwd_kernel<T, 3, false>), grid, block, sh, s, a); break;
+    case 4: hipLaunchKernelGGL((node_fwd_kernel<T, 4, false>), grid, block, sh, s, a); break;
+    default: hipLaunchKernelGGL((node_fwd_kernel<T, 0, false>), grid, block, sh, s, a); break;
   }
   return hipGetLastError();
 }
@@ -579,6 +647,28 @@ __global__ __launch_bounds__(1024) void misfit_kernel(const double* __restrict__
   if (threadIdx.x == 0) *J = (accumulate ? *J : 0.0) + 0.5 * dt * red[0];
 }
 
+// src[q][k][bp] = sum_jd det_sp[jd][bp] r(q, jd, K - k), k = 0..K, with
+// r(q, jd, n) = G[q][jd][n-1] - Gm[q][jd][n-1] for n >= 1 and r(., ., 0) = 0
+__global__ void cadj_source_kernel(const double* __restrict__ G, const double* __restrict__ Gm,
+                                   const double* __restrict__ sp, double* __restrict__ src, int q0, int Nq, int Nd,
+                                   int K, int nb, int rowlen) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)(K + 1) * nb;
+  if (t >= (int64_t)Nq * per) return;
+  const int q = q0 + (int)(t / per);
+  const int64_t r = t % per;
+  const int k = (int)(r / nb);
+  const int bp = (int)(r % nb);
+  const int n = K - k;
+  double acc = 0.0;
+  if (n >= 1)
+    for (int jd = 0; jd < Nd; ++jd) {
+      const int64_t gi = ((int64_t)q * Nd + jd) * K + n - 1;
+      acc += sp[(int64_t)jd * nb + bp] * (G[gi] - Gm[gi]);
+    }
+  src[((int64_t)q * (K + 1) + k) * rowlen + bp] = acc;
+}
+
 __global__ void grad_reduce_kernel(const double* __restrict__ ga, const double* __restrict__ gb, double* __restrict__ da,
                                    double* __restrict__ db, int Nq, int64_t Nn) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -655,6 +745,14 @@ hipError_t launch_misfit(const Plan& p, const double* G, const double* Gm, doubl
   const int64_t off = p.cq0 * p.Nd * (int64_t)K;
   hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(1024), 0, s, G + off, Gm + off, Gbar + off, J,
                      p.cnq * p.Nd * (int64_t)K, p.prob.dt, p.cq0 > 0 ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_cadj_source(const Plan& p, const double* G, const double* Gm, double* src, int K, hipStream_t s) {
+  const int64_t total = p.cnq * (int64_t)(K + 1) * p.nb;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(cadj_source_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, G, Gm, p.dev.det_sp,
+                     src, (int)p.cq0, (int)p.cnq, (int)p.Nd, K, (int)p.nb, (int)(4 * p.npos));
   return hipGetLastError();
 }
 

@@ -227,7 +227,7 @@ static bool validate(const rte_problem* p, const rte_beam* beams, int64_t nbm, c
 
 static void free_tables(DeviceTables& t) {
   void* ps[] = {t.xi, t.eta, t.Wt, t.bc, t.bct, t.kappa, t.det_w, t.beam_sp, t.beam_an, t.beam_tt, t.beam_off,
-                t.slot_m, t.fc_buf};
+                t.slot_m, t.fc_buf, t.det_sp, t.slot_rev};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   t = DeviceTables();
@@ -401,6 +401,23 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
       }
     }
 
+  // ---- continuous adjoint (eq. AdjointProblem): detector footprints at the
+  // boundary positions (inflow source of the reversed problem) and the slot
+  // of the reversed ordinate m + M/2 (pairs psi with u in the gradient)
+  std::vector<double> detsp((size_t)std::max<int64_t>(n_det, 1) * p.nb, 0.0);
+  for (int64_t jd = 0; jd < n_det; ++jd)
+    for (int64_t bp = 0; bp < p.nb; ++bp) {
+      int j, i;
+      if (bp < p.nx) { j = 0; i = (int)bp; }
+      else if (bp < 2 * p.nx) { j = (int)p.ny - 1; i = (int)(bp - p.nx); }
+      else if (bp < 2 * p.nx + p.ny - 2) { i = 0; j = (int)(bp - 2 * p.nx + 1); }
+      else { i = (int)p.nx - 1; j = (int)(bp - 2 * p.nx - (p.ny - 2) + 1); }
+      const double dist = std::hypot(xcoord(i) - dets[jd].x, ycoord(j) - dets[jd].y);
+      detsp[(size_t)jd * p.nb + bp] = window_fn(dist / dets[jd].sigma_d);
+    }
+  std::vector<int32_t> srev((size_t)p.Mpad);
+  for (int s = 0; s < (int)p.Mpad; ++s) srev[s] = s < M ? slot_of[(p.slot_m[s] + M / 2) % M] : s;
+
   // ---- beams grouped per generalised source (CSR)
   std::vector<int> order(n_beams);
   for (int64_t k = 0; k < n_beams; ++k) order[k] = (int)k;
@@ -455,7 +472,8 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
   bool ok = upload(xi, &p.dev.xi) && upload(eta, &p.dev.eta) && upload(Wt, &p.dev.Wt) && upload(bc, &p.dev.bc) &&
             upload(bct, &p.dev.bct) && upload(kappa, &p.dev.kappa) && upload(detw, &p.dev.det_w) &&
             upload(bsp, &p.dev.beam_sp) && upload(ban, &p.dev.beam_an) && upload(btt, &p.dev.beam_tt) &&
-            upload(boff, &p.dev.beam_off) && upload(slotm, &p.dev.slot_m) && upload(fcbuf, &p.dev.fc_buf);
+            upload(boff, &p.dev.beam_off) && upload(slotm, &p.dev.slot_m) && upload(fcbuf, &p.dev.fc_buf) &&
+            upload(detsp, &p.dev.det_sp) && upload(srev, &p.dev.slot_rev);
   if (!ok) {
     set_error("device allocation or upload of the plan tables failed");
     free_tables(p.dev);

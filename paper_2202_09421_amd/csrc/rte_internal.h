@@ -77,6 +77,10 @@ struct DeviceTables {
   int32_t* beam_off = nullptr; // [Nq+1] CSR offsets of beams per source
   int32_t* slot_m = nullptr;   // [M] slot -> ordinate index
   double* fc_buf = nullptr;    // FC tables of both directions
+  // continuous adjoint: detector footprint w(|x_b - x_j| / sigma_d) at the
+  // boundary positions, and the slot of the reversed ordinate theta + pi
+  double* det_sp = nullptr;    // [Nd][nb]
+  int32_t* slot_rev = nullptr; // [Mpad] (padding slots map to themselves)
 };
 
 struct Plan {
@@ -184,6 +188,14 @@ struct NodeFwdLaunch {
   void* L_out;         // L^n
   double* flux;        // [Nq][K+1][4][npos] or nullptr (replay)
   int step;            // n (time level of u)
+  // continuous adjoint (the same step applied to psi, the time- and
+  // ordinate-reversed adjoint): inflow source from csrc instead of the beams,
+  // and the gradient terms of the input psi paired with the forward state
+  // upair (u at the same physical time); csrc == nullptr: ordinary forward
+  const double* csrc = nullptr;  // [Nq][K+1][4 npos] (first nb entries used)
+  const void* upair = nullptr;
+  double* ga = nullptr;          // [Nq][ny*nx]
+  double* gb = nullptr;
 };
 hipError_t launch_node_fwd(const Plan& p, const NodeFwdLaunch& L, hipStream_t s);
 
@@ -213,6 +225,9 @@ hipError_t launch_detect(const Plan& p, const double* flux, double* G, int K, hi
 hipError_t launch_inject(const Plan& p, const double* Gbar, double* inj, int K, hipStream_t s);
 hipError_t launch_misfit(const Plan& p, const double* G, const double* Gm, double* Gbar, double* J,
                          int K, hipStream_t s);
+// continuous adjoint inflow source of the current chunk's sources:
+// src[q][k][bp] = sum_j det_sp[j][bp] r_j(t_{K-k}), r(t_n) = G^n - G~^n (n >= 1), r(t_0) = 0
+hipError_t launch_cadj_source(const Plan& p, const double* G, const double* Gm, double* src, int K, hipStream_t s);
 hipError_t launch_grad_reduce(const Plan& p, const double* ga, const double* gb, double* da, double* db,
                               hipStream_t s);
 hipError_t launch_unpermute(const Plan& p, const void* state, void* out, hipStream_t s);

@@ -87,6 +87,7 @@ def lib():
         L.rte_forward.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp, i64, vp]
         L.rte_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp]
         L.rte_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.rte_gradient_continuous.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
         L.rte_plan_set_graph.argtypes = [vp, ctypes.c_int]
         L.rte_batch_create.argtypes = [ctypes.POINTER(vp), i64, ctypes.POINTER(vp)]
         L.rte_batch_destroy.argtypes = [vp]
@@ -103,7 +104,7 @@ def lib():
         for f in ("rte_plan_create", "rte_plan_destroy", "rte_plan_info", "rte_workspace_bytes", "rte_forward",
                   "rte_adjoint", "rte_gradient", "rte_profile_enable", "rte_profile_read", "rte_plan_set_graph",
                   "rte_batch_create", "rte_batch_destroy", "rte_batch_gradient", "rte_plan_get_schedule",
-                  "rte_plan_set_schedule", "rte_plan_autotune", "rte_plan_time_kernels"):
+                  "rte_plan_set_schedule", "rte_plan_autotune", "rte_plan_time_kernels", "rte_gradient_continuous"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -320,6 +321,21 @@ class Plan:
         ws = self.workspace(True)
         _check(lib().rte_gradient(self._h, _ptr(a), _ptr(b), _ptr(gm), _ptr(J), _ptr(da), _ptr(db), _ptr(G),
                                   _ptr(ws), ws.numel(), _stream()))
+        return J, da, db, G
+
+
+    def gradient_continuous(self, mu_a, mu_s, G_meas):
+        """J, dJ/dmu_a, dJ/dmu_s, G by the paper's continuous adjoint
+        (rte_gradient_continuous): equal to `gradient` in J and G, and in the
+        gradient maps to discretisation error.  Always eager."""
+        a, b = self._medium(mu_a, mu_s)
+        gm = torch.as_tensor(G_meas, dtype=torch.float64, device=self.device).contiguous()
+        ny, nx = self.spec.Ny + 1, self.spec.Nx + 1
+        mk = lambda *sh: torch.empty(sh, dtype=torch.float64, device=self.device)
+        J, da, db, G = mk(1), mk(ny, nx), mk(ny, nx), mk(self.Nq, self.Nd, self.spec.K)
+        ws = self.workspace(True)
+        _check(lib().rte_gradient_continuous(self._h, _ptr(a), _ptr(b), _ptr(gm), _ptr(J), _ptr(da), _ptr(db),
+                                             _ptr(G), _ptr(ws), ws.numel(), _stream()))
         return J, da, db, G
 
 
