@@ -341,6 +341,46 @@ def full_workload(which, dtype_names, K_override, log_fn, plain=True):
             "runs": runs}
 
 
+def inverse_workload(N, iters, log_fn):
+    """The outer inverse loop (L-BFGS-B over a, Algorithm algfcinv) on the
+    synthetic inverse phantom, TS (8 single-beam sources) against MSS (2
+    staggered combinations of 4 beams): E(i) and elapsed time per iteration
+    and the time each needs to reach the same error."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2202_09421_amd import rte
+    from paper_2202_09421_amd.inverse import plan_objective, reconstruct
+
+    runs = {}
+    for mode in ("ts", "mss"):
+        spec, a_bg, lo, hi = W.inverse_phantom(mode, N=N)
+        plan = rte.Plan(spec, torch.float64)
+        G = plan.forward(spec.mu_a, spec.mu_s)
+        Gm = (G * torch.tensor(W.measured_noise(11, tuple(G.shape)), device="cuda")).contiguous()
+        plan.autotune(torch.tensor(a_bg, device="cuda"), torch.tensor(spec.mu_s, device="cuda"), cache=False)
+        fn = plan_objective(plan, spec.mu_s, Gm, graph=True)
+        fn(a_bg)  # records the graph
+        torch.cuda.synchronize()
+        a, hist = reconstruct(fn, a_bg, lo, hi, max_iter=iters, a_true=spec.mu_a, dx=spec.dx, dy=spec.dy)
+        units = (spec.Nx + 1) * (spec.Ny + 1) * spec.M * spec.K * spec.Nq
+        log_fn("bench: inverse %s: %d sources, %d steps, %d iterations, %d gradients, %.1f s, E %.4f -> %.4f" % (
+            mode, spec.Nq, spec.K, len(hist) - 1, hist[-1]["evals"], hist[-1]["seconds"], hist[0]["E"], hist[-1]["E"]))
+        runs[mode] = {"sources": spec.Nq, "time_steps": spec.K, "units_per_gradient": units,
+                      "iterations": len(hist) - 1, "gradients": hist[-1]["evals"], "seconds": hist[-1]["seconds"],
+                      "E": [round(h["E"], 5) for h in hist], "t": [round(h["seconds"], 3) for h in hist]}
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
+    target = max(runs["ts"]["E"][-1], runs["mss"]["E"][-1])
+    reach = {m: next(t for e, t in zip(r["E"], r["t"]) if e <= target) for m, r in runs.items()}
+    return {"workload": "inverse phantom 2x2 cm, %dx%d nodes, 16 ordinates, 16 detectors, 10%% noise" % (N + 1, N + 1),
+            "optimizer": "L-BFGS-B, a in [0.1, 1] /cm, from the background", "runs": runs,
+            "E_target": target, "seconds_to_E_target": reach,
+            "ts_over_mss_time": reach["ts"] / max(reach["mss"], 1e-9)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -361,7 +401,9 @@ def main():
                     help="one eager gradient only (no graph, no events): the command profiled for counters")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized tensor 5 times (calibrates the HBM byte counters)")
-    ap.add_argument("--workload", choices=["gradient", "mss-full", "neck"], default="gradient",
+    ap.add_argument("--inverse-n", type=int, default=128, help="with --workload inverse: intervals per side")
+    ap.add_argument("--inverse-iters", type=int, default=20, help="with --workload inverse: L-BFGS-B iterations")
+    ap.add_argument("--workload", choices=["gradient", "mss-full", "neck", "inverse"], default="gradient",
                     help="gradient (default): the benchmark line; mss-full / neck: one full-size gradient of the "
                          "MSS or neck-phantom workload, batched and plain (prints its own JSON line)")
     ap.add_argument("--workload-steps", type=int, default=0,
@@ -388,6 +430,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("bench: copied %d MiB x 5" % args.copy_calibration)
+        return
+    if args.workload == "inverse":
+        print(json.dumps(inverse_workload(args.inverse_n, args.inverse_iters, log)), flush=True)
         return
     if args.workload != "gradient":
         dts = ["f64", "f32"] if args.workload == "mss-full" else ["f32"]
@@ -442,6 +487,26 @@ def main():
     log("bench: timed %d gradients in %.3f s (J = %.6e)" % (args.steps, elapsed, float(J.item())))
     if not np.isfinite(float(J.item())) or not torch.isfinite(ga).all():
         raise RuntimeError("non-finite gradient")
+
+    # the paper's own gradient (continuous adjoint, always eager) on the same
+    # workload, against the exact discrete one just computed
+    ga_ref, gb_ref = ga.clone(), gb.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Jc, gac, gbc, _ = plan.gradient_continuous(a_bg, b_bg, Gm)
+    torch.cuda.synchronize()
+    cont_s = time.perf_counter() - t0
+    log("bench: continuous-adjoint gradient (eager) %.1f ms" % (1000 * cont_s))
+    cont = {"ms": 1000 * cont_s, "value": nx * ny * spec.M * spec.K * spec.Nq / cont_s,
+            "unit": "cell*ordinate*steps/s", "eager_discrete_ms": 1000 * eager_s,
+            "J_equal": bool(torch.equal(Jc, J)),
+            "dir_derivative_rel_diff": {
+                "da=1": abs(float(gac.sum() - ga_ref.sum())) / abs(float(ga_ref.sum())),
+                "db=1": abs(float(gbc.sum() - gb_ref.sum())) / abs(float(gb_ref.sum()))},
+            "note": "eq. (AdjointProblem) solved by the forward kernels in reversed time and ordinates, "
+                    "eq. (FDwin22) in the node pass; differs from the exact discrete gradient by "
+                    "discretisation error"}
+    del gac, gbc, ga_ref, gb_ref
 
     # (3) per-kernel durations (roofline figures), right after the timed
     #     steps on the same stream: for each kernel class, 20 back-to-back
@@ -499,6 +564,7 @@ def main():
         "path_roofline": {"algorithmic_bytes_per_unit": PATH_WORDS_STORE_ALL * word, "achieved_GB_s": path_gbs,
                           "frac": path_gbs / HBM_PEAK_GBS},
         "kernels": kernels,
+        "continuous_adjoint": cont,
     }
     if args.mss_steps > 0 or args.uneven_scale > 0:
         plan.close()

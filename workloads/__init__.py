@@ -305,6 +305,39 @@ def neck_phantom(N: int = 1024, K: int = 6000) -> ProblemSpec:
                        name="neck-1024x1024-M64-K6000")
 
 
+def inverse_phantom(mode: str = "mss", N: int = 64, M: int = 16, seed: int = 6):
+    """Inverse-problem test bed (Sec. 6 setting on a synthetic phantom):
+    2 x 2 cm, background a = 0.1, b = 20 /cm, g = 0.8, Fresnel n = 1.4, two
+    seeded inclusions with 3x absorption, 8 beams (two per side), 16
+    detectors.  mode "ts": each beam is its own generalised source (8 sources,
+    T = 200 ps); "mss": two combinations of 4 beams (one per side) fired with
+    staggered delays 0, 40, 80, 120 ps (T = 320 ps).
+    Returns (spec with the true medium, background a, lower bound a^l, upper
+    bound a^u)."""
+    L = 2.0
+    rng = np.random.default_rng(seed)
+    X, Y = grid_xy(0.0, L, 0.0, L, N, N)
+    h = L / N
+    a_bg, b_bg = 0.1, 20.0
+    a = np.full(X.shape, a_bg)
+    for (cx, cy, r) in inclusions(rng, L, 2, 0.2, 0.35, margin=0.4):
+        a = a + 2.0 * a_bg * _smooth_indicator(np.hypot(X - cx, Y - cy), r, 2 * h)
+    b = np.full(X.shape, b_bg)
+    beams = []
+    for j in range(8):
+        x, y, th = perimeter_point((j + 0.5) * 1.0, 0, L, 0, L)
+        if mode == "ts":
+            beams.append(Beam(x, y, th, tau=0.0, group=j))
+        else:
+            beams.append(Beam(x, y, th, tau=40.0 * (j // 2), group=j % 2))
+    T = 200.0 if mode == "ts" else 320.0
+    dt = default_dt(h, h, C_LIGHT, a, b)
+    K = int(math.ceil(T / dt))
+    spec = ProblemSpec(0, L, 0, L, N, N, M, K, dt, a, b, beams, perimeter_detectors(16, 0, L, 0, L),
+                       g=0.8, n_in=1.4, name="inverse-%s-%dx%d-M%d" % (mode, N, N, M))
+    return spec, np.full(X.shape, a_bg), a_bg, 1.0
+
+
 def small_problem(N=16, M=8, K=40, L=1.0, g=0.5, n_in=1.4, a0=0.5, b0=5.0, seed=0,
                   n_det=4, beams=None, hg_exponent=1.5, heterogeneous=True, Ny=None,
                   dt=None) -> ProblemSpec:
