@@ -147,6 +147,46 @@ int rte_gradient(rte_plan* plan, const void* mu_a, const void* mu_s, const doubl
                  double* J, double* dmu_a, double* dmu_s, double* G, void* workspace,
                  int64_t workspace_bytes, void* stream);
 
+/* A space-time-angle field given as a sum of separable products
+ *   f(x_i, y_j, theta_m, t_n) = sum_k X[k][n+3][i] * Y[k][n+3][j] * Th[k][m]
+ * on the time levels n = -3 .. K (row n+3 of X and Y), nodes i, j and
+ * ordinates m = 0..M-1 in natural order (theta_m = 2 pi m / M).  Device
+ * arrays, FP64: X [rank][K+4][Nx+1], Y [rank][K+4][Ny+1], Th [rank][M].
+ * rank = 0: absent.                                                        */
+typedef struct {
+  int32_t rank;
+  int32_t reserved0;
+  const double* X;
+  const double* Y;
+  const double* Th;
+} rte_separable;
+
+/* Extra data of a forward solve beyond the paper's laser-beam problem, as in
+ * the manufactured-solution problem eq. (RTEdisp) of Sec. 5:
+ *   u0      : device [Nq][Ny+1][Nx+1][M] (plan dtype), initial state (NULL: 0)
+ *   u_hist  : device [3][Nq][Ny+1][Nx+1][M], the states at t_{-1}, t_{-2},
+ *             t_{-3}; the AB4 history starts from L^{-k} = L(u_hist[k-1]) +
+ *             q(t_{-k}) (NULL: zero history, as for the beam problem)
+ *   source  : volumetric source q added to the right-hand side,
+ *             u_t = c (L(u) + q)
+ *   inflow  : data u_b on Gamma_- after every update (with the plan's Fresnel
+ *             reflection, which vanishes for n_in = n_out), replacing the
+ *             beams; rank 0 keeps the beams.
+ * The same fields apply to every generalised source.                       */
+typedef struct {
+  const void* u0;
+  const void* u_hist;
+  rte_separable source;
+  rte_separable inflow;
+} rte_forward_extra;
+
+/* Forward solve with the extra data (Algorithm 1 with q, u0, u_b): outputs
+ * as rte_forward (G, optional u_final); no states are kept.  Workspace:
+ * rte_workspace_bytes(plan, 0).  RTE_EINVAL for a negative rank or a NULL
+ * table of a positive-rank field.                                          */
+int rte_forward_ex(rte_plan* plan, const void* mu_a, const void* mu_s, const rte_forward_extra* extra,
+                   double* G, void* u_final, void* workspace, int64_t workspace_bytes, void* stream);
+
 /* The paper's own gradient (Sec. 3.3): the continuous adjoint problem
  * eq. (AdjointProblem) solved by the forward machinery, then eq. (FDwin22).
  * With s = T - t and reversed ordinates, psi(x, theta, s) = lambda(x,

@@ -32,6 +32,7 @@ struct Ctx {
   const void* mu_a;
   const void* mu_s;
   int64_t S;  // state stride in bytes
+  const rte_forward_extra* ext = nullptr;  // rte_forward_ex: source, inflow data
 };
 
 inline void* at(void* base, int64_t k, int64_t S) { return static_cast<char*>(base) + k * S; }
@@ -61,6 +62,10 @@ int fwd_step(Ctx& c, int n, const void* un, void* unp1, double* flux) {
   nf.L_out = c.ws.lring[n % 3];
   nf.flux = flux;
   nf.step = n;
+  if (c.ext) {
+    nf.vsrc = &c.ext->source;
+    nf.inflow = &c.ext->inflow;
+  }
   TIMED(RTE_K_NODE_FWD, launch_node_fwd(c.p, nf, c.st));
   return RTE_OK;
 }
@@ -328,6 +333,82 @@ int cadj_chunk(Ctx& c) {
       if (rc != RTE_OK) return rc;
     }
   }
+  return RTE_OK;
+}
+
+// ---------------------------------------------------------------- extended forward
+// rte_forward_ex for the current chunk: start-up history L^{-k} from the given
+// states (lines and node pass at time level -k, the state update discarded),
+// initial state, then the time loop with the separable source and inflow.
+int forward_ex_chunk(Ctx& c, void* u_final) {
+  Plan& p = c.p;
+  Workspace& ws = c.ws;
+  hipStream_t st = c.st;
+  const int64_t S = c.S;
+  const rte_forward_extra* ex = c.ext;
+  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
+  const int64_t nat = p.nx * p.ny * p.M * es;  // one source, natural layout
+  for (int k = 0; k < 3; ++k) RTE_CHECK(launch_zero(ws.lring[k], S, st));
+  RTE_CHECK(launch_zero(ws.work_u[0], S, st));
+  if (ex->u_hist) {
+    for (int k = 3; k >= 1; --k) {
+      const char* h = static_cast<const char*>(ex->u_hist) + ((int64_t)(k - 1) * p.Nq + p.cq0) * nat;
+      RTE_CHECK(launch_permute(p, h, ws.work_u[0], st));
+      LineLaunch ll{ws.work_u[0], ws.tx, ws.ty, LINE_FWD, 3};
+      TIMED(RTE_K_LINES_FWD, launch_lines(p, ll, st));
+      void* Lk = ws.lring[(3 - k) % 3];  // L^{-k}: ring slot (-k) mod 3
+      NodeFwdLaunch nf;
+      nf.u = ws.work_u[0];
+      nf.X = ws.tx;
+      nf.Y = ws.ty;
+      nf.L1 = nf.L2 = nf.L3 = Lk;        // read and overwritten by the same lane; update discarded
+      nf.mu_a = c.mu_a;
+      nf.mu_s = c.mu_s;
+      nf.u_out = ws.work_u[1];
+      nf.L_out = Lk;
+      nf.flux = nullptr;
+      nf.step = -k;
+      nf.vsrc = &ex->source;
+      nf.inflow = &ex->inflow;
+      TIMED(RTE_K_NODE_FWD, launch_node_fwd(p, nf, st));
+    }
+  }
+  if (ex->u0) {
+    RTE_CHECK(launch_zero(ws.work_u[0], S, st));
+    RTE_CHECK(launch_permute(p, static_cast<const char*>(ex->u0) + p.cq0 * nat, ws.work_u[0], st));
+  } else if (ex->u_hist) {
+    RTE_CHECK(launch_zero(ws.work_u[0], S, st));
+  }
+  for (int n = 0; n < p.K; ++n) {
+    int rc = fwd_step(c, n, ws.work_u[n & 1], ws.work_u[(n + 1) & 1], ws.flux);
+    if (rc != RTE_OK) return rc;
+  }
+  if (u_final) RTE_CHECK(launch_unpermute(p, ws.work_u[p.K & 1], u_final, st));
+  return RTE_OK;
+}
+
+int run_forward_ex(Plan& p, const void* mu_a, const void* mu_s, const rte_forward_extra* ex, double* G,
+                   void* u_final, void* wsp, int64_t wsb, hipStream_t st) {
+  Workspace ws;
+  if (!map_or_fail(p, wsp, wsb, false, &ws)) return RTE_ENOMEM;
+  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
+  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  Ctx c{p, ws, st, mu_a, mu_s, S};
+  c.ext = ex;
+  p.have_forward = false;
+  RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
+  const int64_t nc = n_chunks(p);
+  for (int64_t k = 0; k < nc; ++k) {
+    set_chunk(p, k);
+    int rc = forward_ex_chunk(c, u_final);
+    if (rc == RTE_OK && G) rc = launch_detect(p, ws.flux, G, (int)p.K, st) == hipSuccess ? RTE_OK : RTE_EDEVICE;
+    if (rc != RTE_OK) {
+      reset_chunk(p);
+      if (rc == RTE_EDEVICE && last_error()[0] == '\0') set_error("detector kernel launch failed");
+      return rc;
+    }
+  }
+  reset_chunk(p);
   return RTE_OK;
 }
 
@@ -748,6 +829,34 @@ int rte_gradient(rte_plan* h, const void* mu_a, const void* mu_s, const double* 
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (p.use_graph) return graph_gradient(p, a, st);
     return enqueue_gradient(p, a, st);
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RTE_EINVAL;
+  }
+}
+
+static bool separable_ok(const rte_separable& f, const char* what) {
+  if (f.rank < 0) {
+    set_error(std::string(what) + ".rank must be >= 0");
+    return false;
+  }
+  if (f.rank > 0 && (!f.X || !f.Y || !f.Th)) {
+    set_error(std::string(what) + ": X, Y and Th are required when rank > 0");
+    return false;
+  }
+  return true;
+}
+
+int rte_forward_ex(rte_plan* h, const void* mu_a, const void* mu_s, const rte_forward_extra* extra, double* G,
+                   void* u_final, void* workspace, int64_t workspace_bytes, void* stream) {
+  if (!nonnull(h, "plan") || !nonnull(mu_a, "mu_a") || !nonnull(mu_s, "mu_s") || !nonnull(extra, "extra") ||
+      !nonnull(workspace, "workspace"))
+    return RTE_EINVAL;
+  if (!separable_ok(extra->source, "source") || !separable_ok(extra->inflow, "inflow")) return RTE_EINVAL;
+  try {
+    set_error("");
+    return run_forward_ex(*reinterpret_cast<Plan*>(h), mu_a, mu_s, extra, G, u_final, workspace, workspace_bytes,
+                          static_cast<hipStream_t>(stream));
   } catch (const std::exception& e) {
     set_error(e.what());
     return RTE_EINVAL;

@@ -163,6 +163,9 @@ struct NodeFwdArgs {
   // reversed-ordinate slots, gradient maps, quadrature dtheta dx dy dt
   const double* csrc; const T* upair; const int32_t* slot_rev; double* ga; double* gb;
   double quad;
+  // extended forward (EXT): separable source and inflow tables, ordinate of each slot
+  rte_separable vsrc, inflow;
+  const int32_t* slot_m;
   NodeGeom geo;
   int step;
   double cdt;
@@ -175,8 +178,22 @@ struct NodeFwdArgs {
 // eq. (FDwin22) terms of its input psi paired with upair (u at the same
 // physical time, ordinate theta + pi) to the gradient maps:
 //   ga -= quad sum psi u~,  gb += quad sum ((W psi) - psi) u~.
-template <typename T, int RTC, bool CADJ>
+// MODE 0: the beam problem; MODE 1: CADJ (above); MODE 2: EXT, the
+// extended forward: q = sum_k X_k Y_k Th_k is added to L^n, and on inflow
+// entries the separable data replace the beams (when inflow.rank > 0).
+// Time level n of the tables is row n + 3 (the start-up passes use n < 0).
+__device__ __forceinline__ double sep_value(const rte_separable& f, int row, int K4, int i, int j, int nx, int ny,
+                                            int M, int m) {
+  double acc = 0.0;
+  for (int k = 0; k < f.rank; ++k)
+    acc += f.X[((int64_t)k * K4 + row) * nx + i] * f.Y[((int64_t)k * K4 + row) * ny + j] * f.Th[(int64_t)k * M + m];
+  return acc;
+}
+
+template <typename T, int RTC, int MODE>
 __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwdArgs<T> a) {
+  constexpr bool CADJ = MODE == 1;
+  constexpr bool EXT = MODE == 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const NodeGeom& G = a.geo;
   const TileLane t = tile_lane(G);
@@ -223,12 +240,23 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
   __syncthreads();
   const typename Mfma<T>::acc_t S = scatter_tile<T, RTC>(Bs, af, a.Wt, G, t);
 
-  // L^n and the AB4 combination
+  // L^n (plus the volumetric source) and the AB4 combination
   const T cdt = T(a.cdt);
+  T qv[4] = {T(0), T(0), T(0), T(0)};
+  if constexpr (EXT) {
+    if (a.vsrc.rank > 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (gv[v])
+          qv[v] = T(sep_value(a.vsrc, a.step + 3, G.K1 + 3, t.i, t.j, G.nx, G.ny, G.M,
+                              a.slot_m[4 * (4 * t.rt + v) + t.r]));
+    }
+  }
   T un[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const T Ln = B * S[v] - (A + B) * u[v] + X[v] + Y[v];
+    T Ln = B * S[v] - (A + B) * u[v] + X[v] + Y[v];
+    if constexpr (EXT) Ln += qv[v];
     un[v] = u[v] + cdt * (T(kChi0) * Ln + T(kChi1) * L1[v] + T(kChi2) * L2[v] + T(kChi3) * L3[v]);
     if (gv[v]) sto(Loq, off[v], Ln);
   }
@@ -258,8 +286,11 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
         if (on)
           src[v] = T((1.0 - br[v].coef_a - br[v].coef_b) *
                      a.csrc[((int64_t)q * G.K1 + a.step + 1) * 4 * G.npos + bp]);
+      } else if (EXT && a.inflow.rank > 0) {
+        if (on && br[v].flag)
+          src[v] = T(sep_value(a.inflow, a.step + 4, G.K1 + 3, t.i, t.j, G.nx, G.ny, G.M, a.slot_m[s]));
       } else {
-        if (on)
+        if (on && a.step >= 0)
           for (int b = b0; b < b1; ++b)
             src[v] += T(a.beam_sp[(int64_t)b * G.nb + bp] * a.beam_an[b * G.M + s]) * T(a.beam_tt[(int64_t)b * G.K1 + a.step + 1]);
       }
@@ -525,6 +556,26 @@ static dim3 node_grid(const Plan& p, const NodeGeom& g) {
   return dim3((unsigned)((tiles + g.NT - 1) / g.NT), (unsigned)p.cnq);
 }
 
+template <typename T, int MODE>
+static void launch_node_fwd_rt(const NodeFwdArgs<T>& a, dim3 grid, dim3 block, size_t sh, hipStream_t s) {
+  switch (a.geo.RT) {
+    case 1: hipLaunchKernelGGL((node_fwd_kernel<T, 1, MODE>), grid, block, sh, s, a); break;
+    case 2: hipLaunchKernelGGL((node_fwd_kernel<T, 2, MODE>), grid, block, sh, s, a); break;
+    case 3: hipLaunchKernelGGL((node_fwd_kernel<T, 3, MODE>), grid, block, sh, s, a); break;
+    case 4: hipLaunchKernelGGL((node_fwd_kernel<T, 4, MODE>), grid, block, sh, s, a); break;
+    default: hipLaunchKernelGGL((node_fwd_kernel<T, 0, MODE>), grid, block, sh, s, a); break;
+  }
+}
+
+template <typename T>
+static hipError_t launch_node_fwd_mode(int mode, const NodeFwdArgs<T>& a, dim3 grid, dim3 block, size_t sh,
+                                       hipStream_t s) {
+  if (mode == 1) launch_node_fwd_rt<T, 1>(a, grid, block, sh, s);
+  else if (mode == 2) launch_node_fwd_rt<T, 2>(a, grid, block, sh, s);
+  else launch_node_fwd_rt<T, 0>(a, grid, block, sh, s);
+  return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t node_fwd_t(const Plan& p, const NodeFwdLaunch& L, hipStream_t s) {
   NodeFwdArgs<T> a;
@@ -535,6 +586,9 @@ static hipError_t node_fwd_t(const Plan& p, const NodeFwdLaunch& L, hipStream_t 
   a.Wt = p.dev.Wt; a.bc = p.dev.bc; a.kappa = p.dev.kappa;
   a.beam_sp = p.dev.beam_sp; a.beam_an = p.dev.beam_an; a.beam_tt = p.dev.beam_tt; a.beam_off = p.dev.beam_off;
   a.csrc = L.csrc; a.upair = (const T*)L.upair; a.slot_rev = p.dev.slot_rev; a.ga = L.ga; a.gb = L.gb;
+  a.vsrc = L.vsrc ? *L.vsrc : rte_separable{0, 0, nullptr, nullptr, nullptr};
+  a.inflow = L.inflow ? *L.inflow : rte_separable{0, 0, nullptr, nullptr, nullptr};
+  a.slot_m = p.dev.slot_m;
   a.geo = make_geom(p);
   a.step = L.step;
   a.cdt = p.prob.c * p.prob.dt;
@@ -542,25 +596,10 @@ static hipError_t node_fwd_t(const Plan& p, const NodeFwdLaunch& L, hipStream_t 
            ((p.prob.ymax - p.prob.ymin) / (double)p.prob.Ny) * p.prob.dt;
   const dim3 grid = node_grid(p, a.geo), block((unsigned)(64 * a.geo.NT * a.geo.RT));
   const size_t sh = node_shmem(a.geo, sizeof(T));
-  if (L.csrc) {
-    if (!L.upair || !L.ga || !L.gb || L.flux) return hipErrorInvalidValue;
-    switch (a.geo.RT) {
-      case 1: hipLaunchKernelGGL((node_fwd_kernel<T, 1, true>), grid, block, sh, s, a); break;
-      case 2: hipLaunchKernelGGL((node_fwd_kernel<T, 2, true>), grid, block, sh, s, a); break;
-      case 3: hipLaunchKernelGGL((node_fwd_kernel<T, 3, true>), grid, block, sh, s, a); break;
-      case 4: hipLaunchKernelGGL((node_fwd_kernel<T, 4, true>), grid, block, sh, s, a); break;
-      default: hipLaunchKernelGGL((node_fwd_kernel<T, 0, true>), grid, block, sh, s, a); break;
-    }
-    return hipGetLastError();
-  }
-  switch (a.geo.RT) {
-    case 1: hipLaunchKernelGGL((node_fwd_kernel<T, 1, false>), grid, block, sh, s, a); break;
-    case 2: hipLaunchKernelGGL((node_fwd_kernel<T, 2, false>), grid, block, sh, s, a); break;
-    case 3: hipLaunchKernelGGL((node_fwd_kernel<T, 3, false>), grid, block, sh, s, a); break;
-    case 4: hipLaunchKernelGGL((node_fwd_kernel<T, 4, false>), grid, block, sh, s, a); break;
-    default: hipLaunchKernelGGL((node_fwd_kernel<T, 0, false>), grid, block, sh, s, a); break;
-  }
-  return hipGetLastError();
+  if (L.csrc && (!L.upair || !L.ga || !L.gb || L.flux || L.vsrc || L.inflow)) return hipErrorInvalidValue;
+  const int mode = L.csrc ? 1 : ((L.vsrc || L.inflow) ? 2 : 0);
+  if (mode == 2 && (L.step < -3 || L.step >= p.K)) return hipErrorInvalidValue;
+  return launch_node_fwd_mode<T>(mode, a, grid, block, sh, s);
 }
 
 hipError_t launch_node_fwd(const Plan& p, const NodeFwdLaunch& L, hipStream_t s) {
@@ -697,6 +736,20 @@ __global__ void unpermute_kernel(const T* __restrict__ st, T* __restrict__ out, 
   out[((int64_t)q * Nn + gn) * M + slot_m[s]] = v;
 }
 
+template <typename T>
+__global__ void permute_kernel(const T* __restrict__ in, T* __restrict__ st, const int32_t* __restrict__ slot_m, int M,
+                               int nx, int nxp, int64_t Nn, int Nq, int64_t grp_stride, int64_t inst_stride) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)Nq * Nn * M;
+  if (t >= total) return;
+  const int s = (int)(t % M);
+  const int64_t gn = (t / M) % Nn;
+  const int q = (int)(t / (M * Nn));
+  const int g = s / kGroup, r = s % kGroup;
+  const int64_t j = gn / nx, i = gn - j * nx;
+  st[(int64_t)q * inst_stride + (int64_t)g * grp_stride + (j * nxp + i) * kGroup + r] = in[((int64_t)q * Nn + gn) * M + slot_m[s]];
+}
+
 // Zero fill and device copy as kernels (8-byte words): graph captures of the
 // step sequence then hold only kernel nodes.
 __global__ void fill_zero_kernel(unsigned long long* __restrict__ p, int64_t n) {
@@ -761,6 +814,19 @@ hipError_t launch_grad_reduce(const Plan& p, const double* ga, const double* gb,
   const int64_t Nn = p.nx * p.ny;
   hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)((Nn + 255) / 256)), dim3(256), 0, s, ga, gb, da, db,
                      (int)p.Nq, Nn);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute(const Plan& p, const void* in, void* state, hipStream_t s) {
+  const int64_t Nn = p.nx * p.ny;
+  const int64_t total = p.cnq * Nn * p.M;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (p.dtype == RTE_F64)
+    hipLaunchKernelGGL(permute_kernel<double>, grid, dim3(256), 0, s, (const double*)in, (double*)state, p.dev.slot_m,
+                       (int)p.M, (int)p.nx, (int)p.nxp, Nn, (int)p.cnq, p.grp_stride, p.inst_stride);
+  else
+    hipLaunchKernelGGL(permute_kernel<float>, grid, dim3(256), 0, s, (const float*)in, (float*)state, p.dev.slot_m,
+                       (int)p.M, (int)p.nx, (int)p.nxp, Nn, (int)p.cnq, p.grp_stride, p.inst_stride);
   return hipGetLastError();
 }
 

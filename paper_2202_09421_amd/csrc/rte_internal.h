@@ -196,6 +196,10 @@ struct NodeFwdLaunch {
   const void* upair = nullptr;
   double* ga = nullptr;          // [Nq][ny*nx]
   double* gb = nullptr;
+  // extended forward (rte_forward_ex): separable volumetric source and
+  // inflow data; step may be -3..-1 for the start-up history passes
+  const rte_separable* vsrc = nullptr;
+  const rte_separable* inflow = nullptr;
 };
 hipError_t launch_node_fwd(const Plan& p, const NodeFwdLaunch& L, hipStream_t s);
 
@@ -231,6 +235,8 @@ hipError_t launch_cadj_source(const Plan& p, const double* G, const double* Gm, 
 hipError_t launch_grad_reduce(const Plan& p, const double* ga, const double* gb, double* da, double* db,
                               hipStream_t s);
 hipError_t launch_unpermute(const Plan& p, const void* state, void* out, hipStream_t s);
+// natural [cnq][ny][nx][M] (the chunk's sources) into the state layout (padding untouched)
+hipError_t launch_permute(const Plan& p, const void* in, void* state, hipStream_t s);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
 hipError_t launch_copy(void* d, const void* src, int64_t bytes, hipStream_t s);
 

@@ -71,6 +71,16 @@ class rte_schedule(ctypes.Structure):
 _lib = None
 
 
+class rte_separable(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("X", ctypes.c_void_p),
+                ("Y", ctypes.c_void_p), ("Th", ctypes.c_void_p)]
+
+
+class rte_forward_extra(ctypes.Structure):
+    _fields_ = [("u0", ctypes.c_void_p), ("u_hist", ctypes.c_void_p), ("source", rte_separable),
+                ("inflow", rte_separable)]
+
+
 def lib():
     """Load librte.so (raises if it has not been built)."""
     global _lib
@@ -88,6 +98,7 @@ def lib():
         L.rte_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp]
         L.rte_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
         L.rte_gradient_continuous.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.rte_forward_ex.argtypes = [vp, vp, vp, ctypes.POINTER(rte_forward_extra), vp, vp, vp, i64, vp]
         L.rte_plan_set_graph.argtypes = [vp, ctypes.c_int]
         L.rte_batch_create.argtypes = [ctypes.POINTER(vp), i64, ctypes.POINTER(vp)]
         L.rte_batch_destroy.argtypes = [vp]
@@ -104,7 +115,8 @@ def lib():
         for f in ("rte_plan_create", "rte_plan_destroy", "rte_plan_info", "rte_workspace_bytes", "rte_forward",
                   "rte_adjoint", "rte_gradient", "rte_profile_enable", "rte_profile_read", "rte_plan_set_graph",
                   "rte_batch_create", "rte_batch_destroy", "rte_batch_gradient", "rte_plan_get_schedule",
-                  "rte_plan_set_schedule", "rte_plan_autotune", "rte_plan_time_kernels", "rte_gradient_continuous"):
+                  "rte_plan_set_schedule", "rte_plan_autotune", "rte_plan_time_kernels", "rte_gradient_continuous",
+                  "rte_forward_ex"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -323,6 +335,50 @@ class Plan:
                                   _ptr(ws), ws.numel(), _stream()))
         return J, da, db, G
 
+
+    def forward_ex(self, mu_a, mu_s, u0=None, u_hist=None, source=None, inflow=None, want_u_final=True):
+        """rte_forward_ex: forward solve with an initial state u0 [Nq, ny, nx, M],
+        start-up states u_hist [3, Nq, ny, nx, M] (t_{-1}, t_{-2}, t_{-3}), a
+        volumetric source and inflow data, each a separable field (X [R, K+4, nx],
+        Y [R, K+4, ny], Th [R, M]) on the time levels -3..K, or None."""
+        a, b = self._medium(mu_a, mu_s)
+        keep = []
+
+        def dev(x, dtype):
+            if x is None:
+                return None
+            t = torch.as_tensor(x, dtype=dtype, device=self.device).contiguous()
+            keep.append(t)
+            return t
+
+        def sep(f):
+            out = rte_separable()
+            if f is None:
+                return out
+            X, Y, Th = (dev(v, torch.float64) for v in f)
+            K4, nx, ny = self.spec.K + 4, self.spec.Nx + 1, self.spec.Ny + 1
+            R = X.shape[0]
+            if X.shape != (R, K4, nx) or Y.shape != (R, K4, ny) or Th.shape != (R, self.spec.M):
+                raise ValueError("separable field shapes must be [R, K+4, nx], [R, K+4, ny], [R, M]")
+            out.rank, out.X, out.Y, out.Th = R, _ptr(X), _ptr(Y), _ptr(Th)
+            return out
+
+        ex = rte_forward_extra()
+        ex.u0 = _ptr(dev(u0, self.dtype)) if u0 is not None else None
+        ex.u_hist = _ptr(dev(u_hist, self.dtype)) if u_hist is not None else None
+        ex.source = sep(source)
+        ex.inflow = sep(inflow)
+        G = torch.empty((self.Nq, self.Nd, self.spec.K), dtype=torch.float64, device=self.device)
+        uK = None
+        if want_u_final:
+            uK = torch.empty((self.Nq, self.spec.Ny + 1, self.spec.Nx + 1, self.spec.M), dtype=self.dtype,
+                             device=self.device)
+        ws = self.workspace(False)
+        _check(lib().rte_forward_ex(self._h, _ptr(a), _ptr(b), ctypes.byref(ex), _ptr(G), _ptr(uK), _ptr(ws),
+                                    ws.numel(), _stream()))
+        # the tables in `keep` may be released now: later allocations reuse
+        # their memory in stream order, after these kernels
+        return (G, uK) if want_u_final else G
 
     def gradient_continuous(self, mu_a, mu_s, G_meas):
         """J, dJ/dmu_a, dJ/dmu_s, G by the paper's continuous adjoint
