@@ -381,6 +381,58 @@ def inverse_workload(N, iters, log_fn):
             "ts_over_mss_time": reach["ts"] / max(reach["mss"], 1e-9)}
 
 
+def mms_workload(log_fn):
+    """The manufactured-solution convergence study of Sec. 5 (Fig. 4) on the
+    device: max flux error at T = 0.5 ps on [0, 3]^2 (a = 0.35, b = 20 /cm,
+    g = 0) under refinement of h, dt and the ordinates, each with the other
+    two fine.  Errors against the exact flux k_Phi e^{-(x-T)^2-(y-T)^2}."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2202_09421_amd import rte
+    from paper_2202_09421_amd.mms import k_phi, manufactured_inputs
+
+    A, B = 0.35, 20.0
+
+    def err(N, M, dt, T=0.5):
+        K = int(round(T / dt))
+        sp = W.small_problem(N=N, M=M, K=K, L=3.0, g=0.0, n_in=1.0, dt=dt, heterogeneous=False, a0=A,
+                             b0=B).with_(n_out=1.0)
+        plan = rte.Plan(sp, torch.float64)
+        u0, uh, src, inflow = manufactured_inputs(sp, A, B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, uK = plan.forward_ex(sp.mu_a, sp.mu_s, u0=u0, u_hist=uh, source=src, inflow=inflow)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        flux = (2.0 * math.pi / M) * uK[0].sum(dim=-1).cpu().numpy()
+        x = np.arange(N + 1) * sp.dx
+        X, Y = np.meshgrid(x, x)
+        exact = k_phi() * np.exp(-(X - K * dt) ** 2 - (Y - K * dt) ** 2)
+        plan.close()
+        return float(np.abs(flux - exact).max()), sec
+
+    def series(name, cases):
+        rows = []
+        for (N, M, dt) in cases:
+            e, sec = err(N, M, dt)
+            rows.append({"N": N, "M": M, "dt": dt, "max_flux_error": e, "seconds": round(sec, 3)})
+            log_fn("bench: mms %s N=%d M=%d dt=%g: error %.3e" % (name, N, M, dt, e))
+        for r0, r1 in zip(rows, rows[1:]):
+            key = {"space": "N", "time": "dt", "angle": "M"}[name]
+            ratio = r0[key] / r1[key] if name == "time" else r1[key] / r0[key]
+            r1["observed_order"] = math.log(r0["max_flux_error"] / r1["max_flux_error"]) / math.log(ratio)
+        return rows
+
+    return {"workload": "manufactured solution (Sec. 5), [0,3]^2, T = 0.5 ps, a = 0.35, b = 20 /cm, g = 0",
+            "space": series("space", [(N, 32, 0.0005) for N in (32, 64, 128, 256)]),
+            "time": series("time", [(128, 32, dt) for dt in (0.04, 0.02, 0.01, 0.005)]),
+            "angle": series("angle", [(128, M, 0.0005) for M in (4, 8, 12, 16)])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,7 +455,7 @@ def main():
                     help="only copy a MIB-sized tensor 5 times (calibrates the HBM byte counters)")
     ap.add_argument("--inverse-n", type=int, default=128, help="with --workload inverse: intervals per side")
     ap.add_argument("--inverse-iters", type=int, default=20, help="with --workload inverse: L-BFGS-B iterations")
-    ap.add_argument("--workload", choices=["gradient", "mss-full", "neck", "inverse"], default="gradient",
+    ap.add_argument("--workload", choices=["gradient", "mss-full", "neck", "inverse", "mms"], default="gradient",
                     help="gradient (default): the benchmark line; mss-full / neck: one full-size gradient of the "
                          "MSS or neck-phantom workload, batched and plain (prints its own JSON line)")
     ap.add_argument("--workload-steps", type=int, default=0,
@@ -430,6 +482,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("bench: copied %d MiB x 5" % args.copy_calibration)
+        return
+    if args.workload == "mms":
+        print(json.dumps(mms_workload(log)), flush=True)
         return
     if args.workload == "inverse":
         print(json.dumps(inverse_workload(args.inverse_n, args.inverse_iters, log)), flush=True)
