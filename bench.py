@@ -463,8 +463,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="with --workload mss-full/neck: skip the plain run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
-              "(the multi-GPU sharding is a design, not part of this build).", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver runs on a single MI355X "
+              "(sharding over several GPUs is a design, not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

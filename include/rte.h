@@ -50,7 +50,7 @@ typedef enum {
   RTE_EINVAL = -1,       /* invalid argument or problem description          */
   RTE_ENOMEM = -2,       /* workspace too small / allocation failed          */
   RTE_EDEVICE = -3,      /* HIP runtime error                                */
-  RTE_EUNSUPPORTED = -5, /* valid request outside what this build implements */
+  RTE_EUNSUPPORTED = -5, /* valid request outside what the library implements */
   RTE_ESTATE = -6        /* call order violated (e.g. adjoint before forward)*/
 } rte_status;
 

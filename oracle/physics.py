@@ -14,7 +14,7 @@ Passages followed:
                                Sec. 5 eq. (sourcelab).
   detectors                    Sec. 3.1, eq. (OpMed).
 
-Readings where the paper is silent (each listed in the design doc):
+Readings where the paper is silent:
   * Fresnel reflectance: the textbook unpolarised law from Snell's law with
     n_in inside and n_out outside, total reflection beyond the critical angle.
   * HG exponent: the printed 3/2 (kept as a parameter).

@@ -194,8 +194,7 @@ int run_forward(Plan& p, const void* mu_a, const void* mu_s, double* G, void* u_
                 int64_t wsb, hipStream_t st) {
   Workspace ws;
   if (!map_or_fail(p, wsp, wsb, save != 0, &ws)) return RTE_ENOMEM;
-  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
-  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  const int64_t S = state_stride_bytes(p);
   Ctx c{p, ws, st, mu_a, mu_s, S};
   p.have_forward = false;
   RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
@@ -227,8 +226,7 @@ int run_adjoint(Plan& p, const void* mu_a, const void* mu_s, const double* Gbar,
   }
   Workspace ws;
   if (!map_or_fail(p, wsp, wsb, true, &ws)) return RTE_ENOMEM;
-  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
-  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  const int64_t S = state_stride_bytes(p);
   Ctx c{p, ws, st, mu_a, mu_s, S};
   const int64_t gbytes = p.Nq * p.nx * p.ny * 8;
   RTE_CHECK(launch_zero(ws.ga, gbytes, st));
@@ -391,8 +389,7 @@ int run_forward_ex(Plan& p, const void* mu_a, const void* mu_s, const rte_forwar
                    void* u_final, void* wsp, int64_t wsb, hipStream_t st) {
   Workspace ws;
   if (!map_or_fail(p, wsp, wsb, false, &ws)) return RTE_ENOMEM;
-  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
-  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  const int64_t S = state_stride_bytes(p);
   Ctx c{p, ws, st, mu_a, mu_s, S};
   c.ext = ex;
   p.have_forward = false;
@@ -429,8 +426,7 @@ struct GradArgs {
 int enqueue_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
   Workspace ws;
   if (!map_or_fail(p, a.ws, a.wsb, true, &ws)) return RTE_ENOMEM;
-  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
-  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  const int64_t S = state_stride_bytes(p);
   Ctx c{p, ws, st, a.mu_a, a.mu_s, S};
   p.have_forward = false;
   RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
@@ -470,8 +466,7 @@ int enqueue_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
 int enqueue_gradient_continuous(Plan& p, const GradArgs& a, hipStream_t st) {
   Workspace ws;
   if (!map_or_fail(p, a.ws, a.wsb, true, &ws)) return RTE_ENOMEM;
-  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
-  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  const int64_t S = state_stride_bytes(p);
   Ctx c{p, ws, st, a.mu_a, a.mu_s, S};
   p.have_forward = false;
   RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
@@ -582,8 +577,7 @@ int tune_setup(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t w
     return RTE_ENOMEM;
   }
   p.have_forward = false;
-  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
-  const int64_t S = ((state_elems(p) * es + 255) / 256) * 256;
+  const int64_t S = state_stride_bytes(p);
   const int64_t cap = p.ckpt_every > 0 ? p.ckpt_every + 1 : p.K + 1;
   t->S = S;
   t->nst = (int)std::max<int64_t>(2, std::min<int64_t>(nstates, cap));

@@ -534,6 +534,11 @@ int64_t state_elems(const Plan& p) { return p.chunk * p.inst_stride; }
 
 static int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
+int64_t state_stride_bytes(const Plan& p) {
+  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
+  return align256(state_elems(p) * es);
+}
+
 struct Layout {
   int64_t states, ckpts, work_u, lring, tx, ty, vring, atx, aty, ap1, flux, ga, gb, gbar, scratch, total;
 };
@@ -544,8 +549,7 @@ struct Layout {
 // checkpoints the segment replays need the forward arrays while the adjoint
 // ring and carries are live, so those are separate.
 static Layout layout(const Plan& p, bool adj) {
-  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
-  const int64_t S = align256(state_elems(p) * es);
+  const int64_t S = state_stride_bytes(p);
   const bool ck = p.ckpt_every > 0;
   const int64_t s = p.ckpt_every;
   Layout L{};
@@ -589,8 +593,7 @@ int64_t workspace_bytes(const Plan& p, bool adj) { return layout(p, adj).total; 
 bool map_workspace(const Plan& p, void* base, int64_t bytes, bool adj, Workspace* ws) {
   const Layout L = layout(p, adj);
   if (!base || bytes < L.total) return false;
-  const int64_t es = (p.dtype == RTE_F64) ? 8 : 4;
-  const int64_t S = align256(state_elems(p) * es);
+  const int64_t S = state_stride_bytes(p);
   char* b = static_cast<char*>(base);
   ws->base = b;
   ws->bytes = bytes;

@@ -150,6 +150,8 @@ struct Workspace {
 };
 
 int64_t state_elems(const Plan& p);
+// bytes between consecutive state arrays of the workspace
+int64_t state_stride_bytes(const Plan& p);
 int64_t workspace_bytes(const Plan& p, bool with_adjoint);
 bool map_workspace(const Plan& p, void* base, int64_t bytes, bool with_adjoint, Workspace* ws);
 
