@@ -182,7 +182,7 @@ def mss_comparison(K, dtype_name, log_fn):
             "plain_vs_batched_gradient_rel_diff": max(rel(ga_sum, gab), rel(gb_sum, gbb))}
 
 
-def uneven_comparison(scale, log_fn, count=32):
+def uneven_comparison(scale, log_fn, count=32, dtype_name="f64", keep_gradients=False):
     """The uneven batch (independent instances of different grids, ordinate
     counts and step counts; grids and steps scaled by `scale`): all instances
     in one graph launch with one branch per instance ("batched") against the
@@ -196,23 +196,29 @@ def uneven_comparison(scale, log_fn, count=32):
     from paper_2202_09421_amd import rte
 
     specs = W.uneven_batch(count=count, scale=scale)
+    tdt = torch.float64 if dtype_name == "f64" else torch.float32
+    es = 8 if dtype_name == "f64" else 4
     plans, media, gms, units = [], [], [], 0
     for sp in specs:
         ny, nx = sp.Ny + 1, sp.Nx + 1
-        state = 8 * ny * (((nx + 3) // 4) * 4) * sp.M
+        state = es * ny * (((nx + 3) // 4) * 4) * sp.M
         ck = 0 if (sp.K + 1) * state < 2e9 else max(8, int(math.sqrt(4 * sp.K)))
-        pl = rte.Plan(sp, torch.float64, ckpt_every=ck)
+        pl = rte.Plan(sp, tdt, ckpt_every=ck)
         plans.append(pl)
-        media.append((torch.tensor(sp.mu_a, device="cuda"), torch.tensor(sp.mu_s, device="cuda")))
+        media.append((torch.tensor(sp.mu_a, device="cuda", dtype=tdt), torch.tensor(sp.mu_s, device="cuda", dtype=tdt)))
         gms.append(torch.zeros((1, pl.Nd, sp.K), device="cuda", dtype=torch.float64))
         units += nx * ny * sp.M * sp.K
     batch = rte.Batch(plans)
-    batch.gradient(media, gms)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.gradient(media, gms)
     torch.cuda.synchronize()
+    log_fn("bench: uneven batch (%s): graph recorded and run once in %.1f s" % (dtype_name, time.perf_counter() - t0))
+    t0 = time.perf_counter()
+    Jb, dab, dbb, _ = batch.gradient(media, gms)
+    torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    grads = [(a.cpu().double().numpy().copy(), b.cpu().double().numpy().copy()) for a, b in zip(dab, dbb)] \
+        if keep_gradients else None
     log_fn("bench: uneven batch of %d instances, one graph launch: %.1f ms" % (len(plans), 1000 * tb))
     for pl in plans:
         pl.set_graph(True)
@@ -229,13 +235,14 @@ def uneven_comparison(scale, log_fn, count=32):
     for pl in plans:
         pl.close()
     torch.cuda.empty_cache()
-    return {"workload": "uneven batch of %d instances" % len(specs), "scale": scale,
+    out = {"workload": "uneven batch of %d instances" % len(specs), "scale": scale,
             "grids": "%d..%d" % (min(s.Nx + 1 for s in specs), max(s.Nx + 1 for s in specs)),
             "ordinates": sorted(set(s.M for s in specs)), "steps": "%d..%d" % (min(s.K for s in specs), max(s.K for s in specs)),
-            "dtype": "f64", "units": units, "batched_value": units / tb, "plain_value": units / tp,
+            "dtype": dtype_name, "units": units, "batched_value": units / tb, "plain_value": units / tp,
             "unit": "cell*ordinate*steps/s", "batched_over_plain": tp / tb,
             "note": "grids and step counts scaled by %.2f from the 128..512-node, 500..3000-step batch; "
                     "instances above 2 GB of states use checkpoints (one forward replay)" % scale}
+    return (out, grads) if keep_gradients else out
 
 
 def full_workload(which, dtype_names, K_override, log_fn, plain=True):
@@ -339,6 +346,23 @@ def full_workload(which, dtype_names, K_override, log_fn, plain=True):
             "launch": "eager (one stream); checkpoints every ckpt_every steps, segments replayed in the adjoint; "
                       + ("one gradient call per chunk of combinations" if split else "one gradient call (all chunks)"),
             "runs": runs}
+
+
+def uneven_full_workload(log_fn):
+    """The uneven batch at full size (32 instances, 129..513 nodes per side,
+    16..64 ordinates, 500..3000 steps), FP64 and FP32, batched (one graph
+    launch) against one after another, and the FP32 gradients against the
+    FP64 ones."""
+    import numpy as np
+    import torch
+
+    r64, g64 = uneven_comparison(1.0, log_fn, dtype_name="f64", keep_gradients=True)
+    torch.cuda.empty_cache()
+    r32, g32 = uneven_comparison(1.0, log_fn, dtype_name="f32", keep_gradients=True)
+    rel = lambda x, y: float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300))
+    diffs = [max(rel(a32, a64), rel(b32, b64)) for (a32, b32), (a64, b64) in zip(g32, g64)]
+    return {"workload": "uneven batch, full size", "f64": r64, "f32": r32,
+            "f32_vs_f64_gradient_rel_l2": {"max": max(diffs), "median": float(np.median(diffs))}}
 
 
 def inverse_workload(N, iters, log_fn):
@@ -455,7 +479,7 @@ def main():
                     help="only copy a MIB-sized tensor 5 times (calibrates the HBM byte counters)")
     ap.add_argument("--inverse-n", type=int, default=128, help="with --workload inverse: intervals per side")
     ap.add_argument("--inverse-iters", type=int, default=20, help="with --workload inverse: L-BFGS-B iterations")
-    ap.add_argument("--workload", choices=["gradient", "mss-full", "neck", "inverse", "mms"], default="gradient",
+    ap.add_argument("--workload", choices=["gradient", "mss-full", "neck", "inverse", "mms", "uneven-full"], default="gradient",
                     help="gradient (default): the benchmark line; mss-full / neck: one full-size gradient of the "
                          "MSS or neck-phantom workload, batched and plain (prints its own JSON line)")
     ap.add_argument("--workload-steps", type=int, default=0,
@@ -482,6 +506,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("bench: copied %d MiB x 5" % args.copy_calibration)
+        return
+    if args.workload == "uneven-full":
+        print(json.dumps(uneven_full_workload(log)), flush=True)
         return
     if args.workload == "mms":
         print(json.dumps(mms_workload(log)), flush=True)
