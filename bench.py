@@ -365,7 +365,7 @@ def uneven_full_workload(log_fn):
             "f32_vs_f64_gradient_rel_l2": {"max": max(diffs), "median": float(np.median(diffs))}}
 
 
-def inverse_workload(N, iters, log_fn):
+def inverse_workload(N, iters, log_fn, n_beams=8, n_comb=2, spacing=40.0):
     """The outer inverse loop (L-BFGS-B over a, Algorithm algfcinv) on the
     synthetic inverse phantom, TS (8 single-beam sources) against MSS (2
     staggered combinations of 4 beams): E(i) and elapsed time per iteration
@@ -379,8 +379,10 @@ def inverse_workload(N, iters, log_fn):
 
     runs = {}
     for mode in ("ts", "mss"):
-        spec, a_bg, lo, hi = W.inverse_phantom(mode, N=N)
-        plan = rte.Plan(spec, torch.float64)
+        spec, a_bg, lo, hi = W.inverse_phantom(mode, N=N, n_beams=n_beams, n_comb=n_comb, spacing=spacing)
+        state = 8 * (N + 1) * (((N + 1 + 3) // 4) * 4) * spec.M
+        chunk = max(1, min(spec.Nq, int(150e9 // ((spec.K + 8) * state))))
+        plan = rte.Plan(spec, torch.float64, combo_chunk=chunk)
         G = plan.forward(spec.mu_a, spec.mu_s)
         Gm = (G * torch.tensor(W.measured_noise(11, tuple(G.shape)), device="cuda")).contiguous()
         plan.autotune(torch.tensor(a_bg, device="cuda"), torch.tensor(spec.mu_s, device="cuda"), cache=False)
@@ -399,7 +401,8 @@ def inverse_workload(N, iters, log_fn):
         torch.cuda.empty_cache()
     target = max(runs["ts"]["E"][-1], runs["mss"]["E"][-1])
     reach = {m: next(t for e, t in zip(r["E"], r["t"]) if e <= target) for m, r in runs.items()}
-    return {"workload": "inverse phantom 2x2 cm, %dx%d nodes, 16 ordinates, 16 detectors, 10%% noise" % (N + 1, N + 1),
+    return {"workload": "inverse phantom 2x2 cm, %dx%d nodes, 16 ordinates, %d beams (MSS: %d combinations, "
+                        "%g ps apart), 16 detectors, 10%% noise" % (N + 1, N + 1, n_beams, n_comb, spacing),
             "optimizer": "L-BFGS-B, a in [0.1, 1] /cm, from the background", "runs": runs,
             "E_target": target, "seconds_to_E_target": reach,
             "ts_over_mss_time": reach["ts"] / max(reach["mss"], 1e-9)}
@@ -479,6 +482,9 @@ def main():
                     help="only copy a MIB-sized tensor 5 times (calibrates the HBM byte counters)")
     ap.add_argument("--inverse-n", type=int, default=128, help="with --workload inverse: intervals per side")
     ap.add_argument("--inverse-iters", type=int, default=20, help="with --workload inverse: L-BFGS-B iterations")
+    ap.add_argument("--inverse-beams", type=int, default=8, help="with --workload inverse: beams on the perimeter")
+    ap.add_argument("--inverse-combinations", type=int, default=2, help="with --workload inverse: MSS combinations")
+    ap.add_argument("--inverse-spacing", type=float, default=40.0, help="with --workload inverse: MSS delay step (ps)")
     ap.add_argument("--workload", choices=["gradient", "mss-full", "neck", "inverse", "mms", "uneven-full"], default="gradient",
                     help="gradient (default): the benchmark line; mss-full / neck: one full-size gradient of the "
                          "MSS or neck-phantom workload, batched and plain (prints its own JSON line)")
@@ -514,7 +520,8 @@ def main():
         print(json.dumps(mms_workload(log)), flush=True)
         return
     if args.workload == "inverse":
-        print(json.dumps(inverse_workload(args.inverse_n, args.inverse_iters, log)), flush=True)
+        print(json.dumps(inverse_workload(args.inverse_n, args.inverse_iters, log, args.inverse_beams,
+                                          args.inverse_combinations, args.inverse_spacing)), flush=True)
         return
     if args.workload != "gradient":
         dts = ["f64", "f32"] if args.workload == "mss-full" else ["f32"]

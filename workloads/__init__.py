@@ -305,13 +305,16 @@ def neck_phantom(N: int = 1024, K: int = 6000) -> ProblemSpec:
                        name="neck-1024x1024-M64-K6000")
 
 
-def inverse_phantom(mode: str = "mss", N: int = 64, M: int = 16, seed: int = 6):
+def inverse_phantom(mode: str = "mss", N: int = 64, M: int = 16, seed: int = 6, n_beams: int = 8,
+                    n_comb: int = 2, spacing: float = 40.0):
     """Inverse-problem test bed (Sec. 6 setting on a synthetic phantom):
     2 x 2 cm, background a = 0.1, b = 20 /cm, g = 0.8, Fresnel n = 1.4, two
-    seeded inclusions with 3x absorption, 8 beams (two per side), 16
-    detectors.  mode "ts": each beam is its own generalised source (8 sources,
-    T = 200 ps); "mss": two combinations of 4 beams (one per side) fired with
-    staggered delays 0, 40, 80, 120 ps (T = 320 ps).
+    seeded inclusions with 3x absorption, n_beams beams evenly spaced on the
+    perimeter, 16 detectors.  mode "ts": each beam is its own generalised
+    source (T = 200 ps); "mss": n_comb combinations, beam j in combination
+    j % n_comb, fired with delay spacing * (j // n_comb) (T = 200 ps plus
+    the last delay).  Default: 8 beams, 2 combinations of 4 beams with
+    delays 0, 40, 80, 120 ps (T = 320 ps).
     Returns (spec with the true medium, background a, lower bound a^l, upper
     bound a^u)."""
     L = 2.0
@@ -324,13 +327,14 @@ def inverse_phantom(mode: str = "mss", N: int = 64, M: int = 16, seed: int = 6):
         a = a + 2.0 * a_bg * _smooth_indicator(np.hypot(X - cx, Y - cy), r, 2 * h)
     b = np.full(X.shape, b_bg)
     beams = []
-    for j in range(8):
-        x, y, th = perimeter_point((j + 0.5) * 1.0, 0, L, 0, L)
+    P = 4 * L
+    for j in range(n_beams):
+        x, y, th = perimeter_point((j + 0.5) * P / n_beams, 0, L, 0, L)
         if mode == "ts":
             beams.append(Beam(x, y, th, tau=0.0, group=j))
         else:
-            beams.append(Beam(x, y, th, tau=40.0 * (j // 2), group=j % 2))
-    T = 200.0 if mode == "ts" else 320.0
+            beams.append(Beam(x, y, th, tau=spacing * (j // n_comb), group=j % n_comb))
+    T = 200.0 if mode == "ts" else 200.0 + spacing * ((n_beams - 1) // n_comb)
     dt = default_dt(h, h, C_LIGHT, a, b)
     K = int(math.ceil(T / dt))
     spec = ProblemSpec(0, L, 0, L, N, N, M, K, dt, a, b, beams, perimeter_detectors(16, 0, L, 0, L),
