@@ -145,13 +145,19 @@ struct L4Smem {
 };
 
 // The transpose (ADJ) and the long lines read the continuation matrix from
-// global memory; the forward pass of lengths up to kLongLine stages it.
+// global memory; the forward pass of lengths up to kLongLine stages it when
+// it has at most kFcTab entries (and reads it from global memory otherwise).
 template <bool ADJ, int N>
 constexpr bool kMxGlobal = ADJ || N > kLongLine;
 
+__host__ __device__ inline int l4_staged_mx(const FcPlanDev& fc, bool mx_global) {
+  const int nmx = 2 * fc.d * (fc.C + fc.E);
+  return (mx_global || nmx > kFcTab) ? 0 : nmx;
+}
+
 template <bool ADJ, int N1, int N2, bool TG>
 inline size_t l4_lds_bytes(const FcPlanDev& fc) {
-  return L4Smem<N1, N2>::bytes(kMxGlobal<ADJ, N1 * N2> ? 0 : 2 * fc.d * (fc.C + fc.E), TG);
+  return L4Smem<N1, N2>::bytes(l4_staged_mx(fc, kMxGlobal<ADJ, N1 * N2>), TG);
 }
 
 __device__ __forceinline__ int rix(int e) { return e + (e >> 4); }
@@ -340,7 +346,7 @@ struct TabRegs {
                        XT = MXG ? 1 : (kFcTab + NTH - 1) / NTH;
   double rr[RT][2], mm[MT], xx[XT];
   __device__ __forceinline__ void load(const FcPlanDev& fc, int lane) {
-    const int nmx = 2 * fc.d * (fc.C + fc.E);
+    const int nmx = l4_staged_mx(fc, MXG);
     if (!TG) {
 #pragma unroll
       for (int t = 0; t < RT; ++t) {
@@ -402,8 +408,9 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
   cx<double>* buf = reinterpret_cast<cx<double>*>(sm);
   cx<double>* roots = reinterpret_cast<cx<double>*>(sm + SM::BUF);
   double* mu = sm + SM::BUF + SM::ROOTS;
-  double* MxS = sm + SM::mx_off(TG);            // staged copy (unused when MXG)
-  const double* Mx = MXG ? a.fc.Mx : MxS;
+  double* MxS = sm + SM::mx_off(TG);            // staged copy (unused when nmx_st == 0)
+  const int nmx_st = l4_staged_mx(a.fc, MXG);
+  const double* Mx = nmx_st ? MxS : a.fc.Mx;
 
   const FcPlanDev& fc = a.fc;
   const int n = fc.n, dd = fc.d, CE = fc.C + fc.E;
@@ -417,7 +424,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
     load_unit<T, TMAX, NTH>(a, d1, n, tid, R1);
     TabRegs<N, NTH, TG, MXG> tab;
     tab.load(fc, tid);
-    tab.stage(roots, mu, MxS, 2 * dd * CE, tid);
+    tab.stage(roots, mu, MxS, nmx_st, tid);
     if (d0.live) {
       stage_unit<T, TMAX, N1, N2, NTH>(R0, d0, a.coef[d0.dir], ADJ, n, tid, buf);
       __syncthreads();
@@ -435,7 +442,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
     {
       TabRegs<N, NTH, TG, MXG> tab;
       tab.load(fc, tid);
-      tab.stage(roots, mu, MxS, 2 * dd * CE, tid);
+      tab.stage(roots, mu, MxS, nmx_st, tid);
     }
     constexpr int CH = 8;
     for (int c0 = 0; c0 < TMAX; c0 += CH) {

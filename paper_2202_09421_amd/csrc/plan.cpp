@@ -176,10 +176,9 @@ static bool build_fc(const rte_problem& pb, int n, double h, std::vector<double>
         buf.push_back((double)acc);
       }
   }
-  // lengths up to kLongLine stage the (C+E) x 2d continuation matrix in LDS;
-  // the transpose keeps its 2d fold values in the C+E extension positions
-  if (!fourstep_split(Np, &fc.n1, &fc.n2) || CE > 64 || CE < 2 * d || (Np <= kLongLine && 2 * d * CE > kFcTab))
-    fc.n1 = fc.n2 = 0;
+  // the extension values are formed by one thread each (CE <= 64); the
+  // transpose keeps its 2d fold values in the C+E extension positions
+  if (!fourstep_split(Np, &fc.n1, &fc.n2) || CE > 64 || CE < 2 * d) fc.n1 = fc.n2 = 0;
   return true;
 }
 
@@ -255,6 +254,10 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
   {
     const int64_t align = (prob->dtype == RTE_F64) ? 4 : 8;  // nodes per 128 bytes of one group
     p.nxp = ((p.nx + align - 1) / align) * align;
+    // a row pitch that is a multiple of 2 KB puts the rows of a node tile's
+    // neighbourhood on few memory channels: pad such rows by 128 bytes
+    const int64_t pitch = p.nxp * kGroup * (prob->dtype == RTE_F64 ? 8 : 4);
+    if (pitch % 2048 == 0) p.nxp += align;
   }
   p.grp_stride = p.ny * p.nxp * kGroup;
   p.inst_stride = p.G * p.grp_stride;

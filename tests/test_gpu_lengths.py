@@ -43,9 +43,22 @@ def rte():
     return R
 
 
+# node counts whose extension E is large (C + E > 38: a continuation matrix
+# of more than 384 entries, read from global memory by the four-step kernel)
+LARGE_E = [(140, 180), (177, 216), (248, 288), (281, 320), (310, 360), (430, 480)]
+
+
+@pytest.mark.parametrize("n,Np", LARGE_E)
+def test_large_extension_matches_oracle(rte, n, Np):
+    _check_length(rte, n, Np)
+
+
 @pytest.mark.parametrize("Np", LENGTHS)
 def test_line_length_matches_oracle(rte, Np):
-    n = Np - FC_C
+    _check_length(rte, Np - FC_C, Np)
+
+
+def _check_length(rte, n, Np):
     spec = W.small_problem(N=n - 1, M=4, K=3, Ny=9, seed=1000 + Np, n_in=1.4, g=0.8)
     o = Oracle(spec)
     od = Oracle(spec, dense_derivative=True)
