@@ -460,6 +460,42 @@ def mms_workload(log_fn):
             "angle": series("angle", [(128, M, 0.0005) for M in (4, 8, 12, 16)])}
 
 
+def lab_flux_workload(log_fn):
+    """The laboratory photon-flux simulation of Sec. 5 (Fig. 6) on the
+    device: scalar-flux snapshots at 30, 100 and 170 ps of the beam entering
+    [0,3]^2 at (1.5, 0); FP64 and FP32, forward throughput and a short
+    profile of each snapshot (peak, centroid height)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2202_09421_amd import rte
+
+    spec, steps = W.lab_flux(200, 32)
+    out = {"workload": "laboratory flux simulation (Sec. 5, Fig. 6): [0,3]^2, 201x201 nodes, 32 ordinates, "
+                       "a = 0.35, b = 20 /cm, g = 0.8, n = 1.4, beam at (1.5, 0), sigma_t = 30 ps",
+           "dt_ps": spec.dt, "K": spec.K, "snapshot_steps": steps, "runs": {}}
+    y = np.linspace(spec.ymin, spec.ymax, spec.Ny + 1)
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        plan = rte.Plan(spec, dt)
+        plan.flux_snapshots(spec.mu_a, spec.mu_s, steps)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi, _ = plan.flux_snapshots(spec.mu_a, spec.mu_s, steps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        phi = phi[0].cpu().numpy()
+        snaps = []
+        for k, n in enumerate(steps):
+            w = np.clip(phi[k], 0, None).sum(1)
+            snaps.append({"t_ps": n * spec.dt, "peak": float(phi[k].max()), "min": float(phi[k].min()),
+                          "centroid_y_cm": float((w * y).sum() / w.sum())})
+        out["runs"][name] = {"seconds": round(sec, 4), "units_per_s": spec.units / sec, "snapshots": snaps}
+        log_fn("bench: lab flux %s: %.3f s, %.3e units/s" % (name, sec, spec.units / sec))
+        plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -485,7 +521,7 @@ def main():
     ap.add_argument("--inverse-beams", type=int, default=8, help="with --workload inverse: beams on the perimeter")
     ap.add_argument("--inverse-combinations", type=int, default=2, help="with --workload inverse: MSS combinations")
     ap.add_argument("--inverse-spacing", type=float, default=40.0, help="with --workload inverse: MSS delay step (ps)")
-    ap.add_argument("--workload", choices=["gradient", "mss-full", "neck", "inverse", "mms", "uneven-full"], default="gradient",
+    ap.add_argument("--workload", choices=["gradient", "mss-full", "neck", "inverse", "mms", "lab-flux", "uneven-full"], default="gradient",
                     help="gradient (default): the benchmark line; mss-full / neck: one full-size gradient of the "
                          "MSS or neck-phantom workload, batched and plain (prints its own JSON line)")
     ap.add_argument("--workload-steps", type=int, default=0,
@@ -518,6 +554,9 @@ def main():
         return
     if args.workload == "mms":
         print(json.dumps(mms_workload(log)), flush=True)
+        return
+    if args.workload == "lab-flux":
+        print(json.dumps(lab_flux_workload(log)), flush=True)
         return
     if args.workload == "inverse":
         print(json.dumps(inverse_workload(args.inverse_n, args.inverse_iters, log, args.inverse_beams,

@@ -162,7 +162,8 @@ typedef struct {
 } rte_separable;
 
 /* Extra data of a forward solve beyond the paper's laser-beam problem, as in
- * the manufactured-solution problem eq. (RTEdisp) of Sec. 5:
+ * the manufactured-solution problem eq. (RTEdisp) of Sec. 5, and scalar-flux
+ * snapshots as in the laboratory simulation of Sec. 5 (Fig. 6):
  *   u0      : device [Nq][Ny+1][Nx+1][M] (plan dtype), initial state (NULL: 0)
  *   u_hist  : device [3][Nq][Ny+1][Nx+1][M], the states at t_{-1}, t_{-2},
  *             t_{-3}; the AB4 history starts from L^{-k} = L(u_hist[k-1]) +
@@ -172,12 +173,23 @@ typedef struct {
  *   inflow  : data u_b on Gamma_- after every update (with the plan's Fresnel
  *             reflection, which vanishes for n_in = n_out), replacing the
  *             beams; rank 0 keeps the beams.
+ *   n_snap, snap_steps, snap_flux : scalar flux (eq. photondensity with the
+ *             trapezoid rule on the uniform ordinates, dtheta sum_m u_m) of the
+ *             states u^n for the n_snap time levels snap_steps[k] in [0, K]
+ *             (host array, any order, repeats allowed), written to the device
+ *             array snap_flux [Nq][n_snap][Ny+1][Nx+1] (FP64, summed in FP64);
+ *             n_snap = 0: none.  RTE_EINVAL for n_snap < 0, a NULL array with
+ *             n_snap > 0, or a level outside [0, K].
  * The same fields apply to every generalised source.                       */
 typedef struct {
   const void* u0;
   const void* u_hist;
   rte_separable source;
   rte_separable inflow;
+  int32_t n_snap;
+  int32_t reserved1;
+  const int32_t* snap_steps;
+  double* snap_flux;
 } rte_forward_extra;
 
 /* Forward solve with the extra data (Algorithm 1 with q, u0, u_b): outputs

@@ -377,8 +377,18 @@ int forward_ex_chunk(Ctx& c, void* u_final) {
   } else if (ex->u_hist) {
     RTE_CHECK(launch_zero(ws.work_u[0], S, st));
   }
+  // scalar-flux snapshots of u^n: out[q][k] for every k with snap_steps[k] == n
+  const int64_t Nn = p.nx * p.ny;
+  auto snap = [&](int n, const void* un) -> int {
+    for (int k = 0; k < ex->n_snap; ++k)
+      if (ex->snap_steps[k] == n)
+        RTE_CHECK(launch_flux_map(p, un, ex->snap_flux + (p.cq0 * ex->n_snap + k) * Nn, ex->n_snap * Nn, st));
+    return RTE_OK;
+  };
+  if (int rc = snap(0, ws.work_u[0])) return rc;
   for (int n = 0; n < p.K; ++n) {
     int rc = fwd_step(c, n, ws.work_u[n & 1], ws.work_u[(n + 1) & 1], ws.flux);
+    if (rc == RTE_OK) rc = snap(n + 1, ws.work_u[(n + 1) & 1]);
     if (rc != RTE_OK) return rc;
   }
   if (u_final) RTE_CHECK(launch_unpermute(p, ws.work_u[p.K & 1], u_final, st));
@@ -847,6 +857,16 @@ int rte_forward_ex(rte_plan* h, const void* mu_a, const void* mu_s, const rte_fo
       !nonnull(workspace, "workspace"))
     return RTE_EINVAL;
   if (!separable_ok(extra->source, "source") || !separable_ok(extra->inflow, "inflow")) return RTE_EINVAL;
+  if (extra->n_snap < 0 || (extra->n_snap > 0 && (!extra->snap_steps || !extra->snap_flux))) {
+    set_error("n_snap must be >= 0, with snap_steps and snap_flux when positive");
+    return RTE_EINVAL;
+  }
+  const int64_t K = reinterpret_cast<Plan*>(h)->K;
+  for (int k = 0; k < extra->n_snap; ++k)
+    if (extra->snap_steps[k] < 0 || extra->snap_steps[k] > K) {
+      set_error("snap_steps entries must lie in [0, K]");
+      return RTE_EINVAL;
+    }
   try {
     set_error("");
     return run_forward_ex(*reinterpret_cast<Plan*>(h), mu_a, mu_s, extra, G, u_final, workspace, workspace_bytes,

@@ -750,6 +750,23 @@ __global__ void permute_kernel(const T* __restrict__ in, T* __restrict__ st, con
   st[(int64_t)q * inst_stride + (int64_t)g * grp_stride + (j * nxp + i) * kGroup + r] = in[((int64_t)q * Nn + gn) * M + slot_m[s]];
 }
 
+// Scalar flux of a state, eq. (photondensity) with the trapezoid rule on the
+// uniform ordinates: phi[q][j][i] = dtheta sum_s u[q][s][j][i] over the M
+// live slots (the sum does not depend on the slot order), accumulated in
+// FP64 in slot order.  Grid: x over nodes of a row, y over rows, z over the
+// chunk's sources.
+template <typename T>
+__global__ void flux_map_kernel(const T* __restrict__ st, double* __restrict__ out, int M, int nx, int nxp,
+                                int64_t grp_stride, int64_t inst_stride, int64_t out_q_stride, double dth) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= nx) return;
+  const int j = (int)blockIdx.y, q = (int)blockIdx.z;
+  const T* p = st + (int64_t)q * inst_stride + ((int64_t)j * nxp + i) * kGroup;
+  double acc = 0.0;
+  for (int s = 0; s < M; ++s) acc += (double)p[(int64_t)(s / kGroup) * grp_stride + s % kGroup];
+  out[(int64_t)q * out_q_stride + (int64_t)j * nx + i] = dth * acc;
+}
+
 // Zero fill and device copy as kernels (8-byte words): graph captures of the
 // step sequence then hold only kernel nodes.
 __global__ void fill_zero_kernel(unsigned long long* __restrict__ p, int64_t n) {
@@ -827,6 +844,19 @@ hipError_t launch_permute(const Plan& p, const void* in, void* state, hipStream_
   else
     hipLaunchKernelGGL(permute_kernel<float>, grid, dim3(256), 0, s, (const float*)in, (float*)state, p.dev.slot_m,
                        (int)p.M, (int)p.nx, (int)p.nxp, Nn, (int)p.cnq, p.grp_stride, p.inst_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_map(const Plan& p, const void* state, double* out, int64_t out_q_stride, hipStream_t s) {
+  if (p.nx > 65535 * 256 || p.ny > 65535 || p.cnq > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((p.nx + 255) / 256), (unsigned)p.ny, (unsigned)p.cnq);
+  const double dth = 6.283185307179586476925 / (double)p.M;  // 2 pi / M
+  if (p.dtype == RTE_F64)
+    hipLaunchKernelGGL(flux_map_kernel<double>, grid, dim3(256), 0, s, (const double*)state, out, (int)p.M,
+                       (int)p.nx, (int)p.nxp, p.grp_stride, p.inst_stride, out_q_stride, dth);
+  else
+    hipLaunchKernelGGL(flux_map_kernel<float>, grid, dim3(256), 0, s, (const float*)state, out, (int)p.M,
+                       (int)p.nx, (int)p.nxp, p.grp_stride, p.inst_stride, out_q_stride, dth);
   return hipGetLastError();
 }
 

@@ -239,6 +239,9 @@ hipError_t launch_grad_reduce(const Plan& p, const double* ga, const double* gb,
 hipError_t launch_unpermute(const Plan& p, const void* state, void* out, hipStream_t s);
 // natural [cnq][ny][nx][M] (the chunk's sources) into the state layout (padding untouched)
 hipError_t launch_permute(const Plan& p, const void* in, void* state, hipStream_t s);
+// scalar flux of the chunk's sources: out[q'][j][i] for q' = 0 .. cnq - 1 at
+// out + q' out_q_stride (the caller offsets out to the chunk's first source)
+hipError_t launch_flux_map(const Plan& p, const void* state, double* out, int64_t out_q_stride, hipStream_t s);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
 hipError_t launch_copy(void* d, const void* src, int64_t bytes, hipStream_t s);
 

@@ -78,7 +78,8 @@ class rte_separable(ctypes.Structure):
 
 class rte_forward_extra(ctypes.Structure):
     _fields_ = [("u0", ctypes.c_void_p), ("u_hist", ctypes.c_void_p), ("source", rte_separable),
-                ("inflow", rte_separable)]
+                ("inflow", rte_separable), ("n_snap", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("snap_steps", ctypes.POINTER(ctypes.c_int32)), ("snap_flux", ctypes.c_void_p)]
 
 
 def lib():
@@ -341,6 +342,18 @@ class Plan:
         start-up states u_hist [3, Nq, ny, nx, M] (t_{-1}, t_{-2}, t_{-3}), a
         volumetric source and inflow data, each a separable field (X [R, K+4, nx],
         Y [R, K+4, ny], Th [R, M]) on the time levels -3..K, or None."""
+        G, uK, _ = self._forward_ex(mu_a, mu_s, u0, u_hist, source, inflow, want_u_final, None)
+        return (G, uK) if want_u_final else G
+
+    def flux_snapshots(self, mu_a, mu_s, steps, u0=None, u_hist=None, source=None, inflow=None):
+        """Scalar flux phi(x, t_n) = dtheta sum_m u_m (eq. photondensity) of the
+        forward states u^n at the time levels `steps` (each in [0, K]), as in
+        Fig. 6: returns (phi [Nq, len(steps), ny, nx] FP64, G).  Other
+        arguments as in forward_ex."""
+        G, _, phi = self._forward_ex(mu_a, mu_s, u0, u_hist, source, inflow, False, steps)
+        return phi, G
+
+    def _forward_ex(self, mu_a, mu_s, u0, u_hist, source, inflow, want_u_final, snap_steps):
         a, b = self._medium(mu_a, mu_s)
         keep = []
 
@@ -368,6 +381,14 @@ class Plan:
         ex.u_hist = _ptr(dev(u_hist, self.dtype)) if u_hist is not None else None
         ex.source = sep(source)
         ex.inflow = sep(inflow)
+        phi = None
+        if snap_steps is not None:
+            steps = np.ascontiguousarray(np.asarray(snap_steps, dtype=np.int32).reshape(-1))
+            phi = torch.empty((self.Nq, steps.size, self.spec.Ny + 1, self.spec.Nx + 1), dtype=torch.float64,
+                              device=self.device)
+            ex.n_snap = steps.size
+            ex.snap_steps = steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            ex.snap_flux = _ptr(phi)
         G = torch.empty((self.Nq, self.Nd, self.spec.K), dtype=torch.float64, device=self.device)
         uK = None
         if want_u_final:
@@ -378,7 +399,7 @@ class Plan:
                                     ws.numel(), _stream()))
         # the tables in `keep` may be released now: later allocations reuse
         # their memory in stream order, after these kernels
-        return (G, uK) if want_u_final else G
+        return G, uK, phi
 
     def gradient_continuous(self, mu_a, mu_s, G_meas):
         """J, dJ/dmu_a, dJ/dmu_s, G by the paper's continuous adjoint

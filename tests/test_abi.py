@@ -77,3 +77,32 @@ def test_library_fc_tables_match_oracle():
     Qo, Ao = blend_table(5, 25)
     assert np.allclose(Q, Qo, rtol=0, atol=1e-15)
     assert np.allclose(A, Ao, rtol=1e-14, atol=1e-14 * np.abs(Ao).max())
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    that a C compiler gives the header's struct of the same name."""
+    import shutil
+    import subprocess
+    from paper_2202_09421_amd import rte
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [rte.rte_problem, rte.rte_beam, rte.rte_detector, rte.rte_schedule, rte.rte_separable,
+               rte.rte_forward_extra]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rte.h"', "int main(void) {"]
+    for S in structs:
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (S.__name__, S.__name__))
+        for f in S._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (S.__name__, f[0], S.__name__, f[0]))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(ln.split() for ln in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                   check=True).stdout.splitlines())
+    for S in structs:
+        assert int(got[S.__name__]) == ctypes.sizeof(S), S.__name__
+        for f in S._fields_:
+            assert int(got["%s.%s" % (S.__name__, f[0])]) == getattr(S, f[0]).offset, (S.__name__, f[0])

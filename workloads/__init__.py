@@ -342,6 +342,26 @@ def inverse_phantom(mode: str = "mss", N: int = 64, M: int = 16, seed: int = 6, 
     return spec, np.full(X.shape, a_bg), a_bg, 1.0
 
 
+def lab_flux(N: int = 200, M: int = 32, times=(30.0, 100.0, 170.0), dt: Optional[float] = None):
+    """The laboratory photon-flux simulation of Sec. 5 (Fig. 6): [0,3]^2 cm,
+    homogeneous a = 0.35 /cm, b = 20 /cm, g = 0.8, n = 1.4, one beam at
+    (1.5, 0) along the inward normal (sigma_x = 0.3 cm, sigma_theta = pi/4,
+    pulse centred at t = 0 with sigma_t = 30 ps).  Returns (spec, steps):
+    K reaches the last snapshot time and steps[k] is the time level nearest
+    times[k]."""
+    L = 3.0
+    a = np.full((N + 1, N + 1), 0.35)
+    b = np.full((N + 1, N + 1), 20.0)
+    h = L / N
+    if dt is None:
+        dt = default_dt(h, h, C_LIGHT, a, b)
+    steps = [int(round(t / dt)) for t in times]
+    spec = ProblemSpec(0, L, 0, L, N, N, M, max(steps), dt, a, b,
+                       [beam_at(1.5, 0.0, 0, L, 0, L, sigma_t=30.0, t0=0.0)], perimeter_detectors(4, 0, L, 0, L),
+                       g=0.8, n_in=1.4, name="lab-flux-%dx%d-M%d" % (N, N, M))
+    return spec, steps
+
+
 def small_problem(N=16, M=8, K=40, L=1.0, g=0.5, n_in=1.4, a0=0.5, b0=5.0, seed=0,
                   n_det=4, beams=None, hg_exponent=1.5, heterogeneous=True, Ny=None,
                   dt=None) -> ProblemSpec:
