@@ -106,7 +106,11 @@ typedef struct rte_plan rte_plan;
 /* Build host tables (ordinates, HG matrix, Fresnel/boundary map, beam and
  * detector tables, FC multipliers and FFT twiddles) and upload them.
  * Nq = 1 + max(beam.group).  Errors: RTE_EINVAL for an invalid description
- * (message says which field), RTE_EDEVICE if the upload fails.           */
+ * (message says which field), among them a beam or detector off the
+ * boundary (Sec. 2.1) and a dt beyond the AB4 stability limit of the
+ * spectral advection, c dt pi sqrt(1/dx^2 + 1/dy^2) > 0.43 (the stiff
+ * limit c dt max(a + b) <~ 0.3 depends on the maps of each call and is the
+ * caller's); RTE_EDEVICE if the upload fails.                            */
 int rte_plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
                     const rte_detector* dets, int64_t n_det, rte_plan** out);
 int rte_plan_destroy(rte_plan* plan);

@@ -205,6 +205,38 @@ static bool validate(const rte_problem* p, const rte_beam* beams, int64_t nbm, c
   else if (nbm < 0 || (nbm > 0 && !beams)) e << "bad beam array";
   else if (nd < 0 || (nd > 0 && !dets)) e << "bad detector array";
   if (e.str().empty()) {
+    // AB4 is stable on the imaginary axis up to |lambda| = 0.43; the spectral
+    // advection -c (xi D_x + eta D_y) has eigenvalues up to
+    // c pi sqrt(1/dx^2 + 1/dy^2) in magnitude (the stiff part c (a + b)
+    // depends on the maps passed to each call and is left to the caller)
+    const double dx = (p->xmax - p->xmin) / (double)p->Nx, dy = (p->ymax - p->ymin) / (double)p->Ny;
+    const double lam = p->c * p->dt * kPi * std::sqrt(1.0 / (dx * dx) + 1.0 / (dy * dy));
+    if (lam > 0.43)
+      e << "dt beyond the AB4 stability limit of the advection: c dt pi sqrt(1/dx^2 + 1/dy^2) = " << lam
+        << " > 0.43";
+  }
+  // beams and detectors sit on the boundary (Sec. 2.1): within 1e-9 of the
+  // domain size of one side, and inside the side's extent
+  auto on_boundary = [&](double x, double y) {
+    const double tol = 1e-9 * std::max(p->xmax - p->xmin, p->ymax - p->ymin);
+    const bool in_x = x >= p->xmin - tol && x <= p->xmax + tol, in_y = y >= p->ymin - tol && y <= p->ymax + tol;
+    return in_x && in_y &&
+           (std::fabs(x - p->xmin) <= tol || std::fabs(x - p->xmax) <= tol || std::fabs(y - p->ymin) <= tol ||
+            std::fabs(y - p->ymax) <= tol);
+  };
+  if (e.str().empty()) {
+    for (int64_t k = 0; k < nbm; ++k)
+      if (!on_boundary(beams[k].x, beams[k].y)) {
+        e << "beam " << k << " is not on the boundary";
+        break;
+      }
+    for (int64_t k = 0; k < nd && e.str().empty(); ++k)
+      if (!on_boundary(dets[k].x, dets[k].y)) {
+        e << "detector " << k << " is not on the boundary";
+        break;
+      }
+  }
+  if (e.str().empty()) {
     for (int64_t k = 0; k < nbm; ++k)
       if (beams[k].group < 0 || beams[k].group > 4096 || !(beams[k].sigma_x > 0) || !(beams[k].sigma_theta > 0) ||
           !(beams[k].sigma_t > 0)) {

@@ -49,6 +49,7 @@ def _bad_problem(**kw):
     ("g", 1.0, "|g|"),
     ("dt", -1.0, "dt and c"),
     ("dtype", 7, "dtype"),
+    ("dt", 50.0, "AB4 stability limit"),
 ])
 def test_plan_create_rejects_bad_input(field, value, msg):
     from paper_2202_09421_amd import rte
@@ -58,6 +59,19 @@ def test_plan_create_rejects_bad_input(field, value, msg):
     rc = L.rte_plan_create(ctypes.byref(prob), beams, nb, dets, nd, ctypes.byref(h))
     assert rc == rte.RTE_EINVAL
     assert msg in L.rte_last_error().decode()
+    assert not h.value
+
+
+@pytest.mark.parametrize("what", ["beam", "detector"])
+def test_plan_create_rejects_sources_off_the_boundary(what):
+    from paper_2202_09421_amd import rte
+    L = _lib()
+    prob, beams, nb, dets, nd, keep = _bad_problem()
+    arr = beams if what == "beam" else dets
+    arr[0].x, arr[0].y = 0.5 * (prob.xmin + prob.xmax), 0.5 * (prob.ymin + prob.ymax)
+    h = ctypes.c_void_p()
+    assert L.rte_plan_create(ctypes.byref(prob), beams, nb, dets, nd, ctypes.byref(h)) == rte.RTE_EINVAL
+    assert "%s 0 is not on the boundary" % what in L.rte_last_error().decode()
     assert not h.value
 
 
