@@ -50,6 +50,8 @@ typedef enum {
   RTE_EINVAL = -1,       /* invalid argument or problem description          */
   RTE_ENOMEM = -2,       /* workspace too small / allocation failed          */
   RTE_EDEVICE = -3,      /* HIP runtime error                                */
+  RTE_EUNSTABLE = -4,    /* non-finite outputs seen by the guard (see
+                            rte_plan_set_guard)                              */
   RTE_EUNSUPPORTED = -5, /* valid request outside what the library implements */
   RTE_ESTATE = -6        /* call order violated (e.g. adjoint before forward)*/
 } rte_status;
@@ -221,6 +223,16 @@ int rte_forward_ex(rte_plan* plan, const void* mu_a, const void* mu_s, const rte
 int rte_gradient_continuous(rte_plan* plan, const void* mu_a, const void* mu_s, const double* G_meas,
                             double* J, double* dmu_a, double* dmu_s, double* G, void* workspace,
                             int64_t workspace_bytes, void* stream);
+
+/* Non-finite guard.  With enable != 0, rte_forward, rte_forward_ex,
+ * rte_adjoint, rte_gradient, rte_gradient_continuous and rte_batch_gradient
+ * scan their FP64 outputs (G, snapshots, J, dmu_a, dmu_s) on the device after
+ * the solve, wait for the stream, and return RTE_EUNSTABLE when any value is
+ * NaN or infinite: a time step beyond the stiff limit c dt max(a + b) ~ 0.3
+ * or a non-finite medium map (one bad node reaches every detector within
+ * two steps, the spectral derivative being global along a line).  The
+ * outputs are still written.  Off by default (no synchronisation).         */
+int rte_plan_set_guard(rte_plan* plan, int enable);
 
 /* Graph mode.  With enable != 0, rte_gradient records its whole launch
  * sequence (forward, misfit, adjoint: ~6 kernels per time step) into one HIP

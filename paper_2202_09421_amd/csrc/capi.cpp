@@ -37,6 +37,27 @@ struct Ctx {
 
 inline void* at(void* base, int64_t k, int64_t S) { return static_cast<char*>(base) + k * S; }
 
+// Non-finite guard: scan the FP64 outputs of a call on the stream, wait, and
+// report RTE_EUNSTABLE if any value is NaN or infinite.
+struct Out {
+  const double* x;
+  int64_t n;
+};
+int guard_check(Plan& p, hipStream_t st, const std::vector<Out>& outs) {
+  if (!p.guard) return RTE_OK;
+  RTE_CHECK(launch_zero(p.dev.guard_flag, 8, st));
+  for (const Out& o : outs)
+    if (o.x) RTE_CHECK(launch_nonfinite(o.x, o.n, p.dev.guard_flag, st));
+  unsigned long long h = 0;
+  RTE_CHECK(hipMemcpyAsync(&h, p.dev.guard_flag, 8, hipMemcpyDeviceToHost, st));
+  RTE_CHECK(hipStreamSynchronize(st));
+  if (h) {
+    set_error("non-finite values in the outputs: dt beyond the stiff stability limit or non-finite medium maps");
+    return RTE_EUNSTABLE;
+  }
+  return RTE_OK;
+}
+
 #define TIMED(cls, expr)                          \
   do {                                            \
     hipEvent_t stop_;                             \
@@ -431,6 +452,10 @@ struct GradArgs {
   int64_t wsb;
 };
 
+std::vector<Out> grad_outputs(const Plan& p, const GradArgs& a) {
+  return {{a.J, 1}, {a.dmu_a, p.nx * p.ny}, {a.dmu_s, p.nx * p.ny}, {a.G, p.Nq * p.Nd * p.K}};
+}
+
 // Forward with kept states, misfit and cotangent, adjoint, chunk by chunk:
 // all enqueued on st.
 int enqueue_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
@@ -797,8 +822,10 @@ int rte_forward(rte_plan* h, const void* mu_a, const void* mu_s, double* G, void
     return RTE_EINVAL;
   try {
     set_error("");
-    return run_forward(*reinterpret_cast<Plan*>(h), mu_a, mu_s, G, u_final, save_states, workspace, workspace_bytes,
-                       static_cast<hipStream_t>(stream));
+    Plan& p = *reinterpret_cast<Plan*>(h);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int rc = run_forward(p, mu_a, mu_s, G, u_final, save_states, workspace, workspace_bytes, st);
+    return rc != RTE_OK ? rc : guard_check(p, st, {{G, p.Nq * p.Nd * p.K}});
   } catch (const std::exception& e) {
     set_error(e.what());
     return RTE_EINVAL;
@@ -812,8 +839,10 @@ int rte_adjoint(rte_plan* h, const void* mu_a, const void* mu_s, const double* G
     return RTE_EINVAL;
   try {
     set_error("");
-    return run_adjoint(*reinterpret_cast<Plan*>(h), mu_a, mu_s, G_bar, dmu_a, dmu_s, workspace, workspace_bytes,
-                       static_cast<hipStream_t>(stream));
+    Plan& p = *reinterpret_cast<Plan*>(h);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int rc = run_adjoint(p, mu_a, mu_s, G_bar, dmu_a, dmu_s, workspace, workspace_bytes, st);
+    return rc != RTE_OK ? rc : guard_check(p, st, {{dmu_a, p.nx * p.ny}, {dmu_s, p.nx * p.ny}});
   } catch (const std::exception& e) {
     set_error(e.what());
     return RTE_EINVAL;
@@ -831,8 +860,8 @@ int rte_gradient(rte_plan* h, const void* mu_a, const void* mu_s, const double* 
     Plan& p = *reinterpret_cast<Plan*>(h);
     GradArgs a{mu_a, mu_s, G_meas, J, dmu_a, dmu_s, G, workspace, workspace_bytes};
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (p.use_graph) return graph_gradient(p, a, st);
-    return enqueue_gradient(p, a, st);
+    const int rc = p.use_graph ? graph_gradient(p, a, st) : enqueue_gradient(p, a, st);
+    return rc != RTE_OK ? rc : guard_check(p, st, grad_outputs(p, a));
   } catch (const std::exception& e) {
     set_error(e.what());
     return RTE_EINVAL;
@@ -869,8 +898,12 @@ int rte_forward_ex(rte_plan* h, const void* mu_a, const void* mu_s, const rte_fo
     }
   try {
     set_error("");
-    return run_forward_ex(*reinterpret_cast<Plan*>(h), mu_a, mu_s, extra, G, u_final, workspace, workspace_bytes,
-                          static_cast<hipStream_t>(stream));
+    Plan& p = *reinterpret_cast<Plan*>(h);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int rc = run_forward_ex(p, mu_a, mu_s, extra, G, u_final, workspace, workspace_bytes, st);
+    return rc != RTE_OK ? rc
+                        : guard_check(p, st, {{G, p.Nq * p.Nd * p.K},
+                                              {extra->snap_flux, p.Nq * extra->n_snap * p.nx * p.ny}});
   } catch (const std::exception& e) {
     set_error(e.what());
     return RTE_EINVAL;
@@ -888,7 +921,9 @@ int rte_gradient_continuous(rte_plan* h, const void* mu_a, const void* mu_s, con
     set_error("");
     Plan& p = *reinterpret_cast<Plan*>(h);
     GradArgs a{mu_a, mu_s, G_meas, J, dmu_a, dmu_s, G, workspace, workspace_bytes};
-    return enqueue_gradient_continuous(p, a, static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int rc = enqueue_gradient_continuous(p, a, st);
+    return rc != RTE_OK ? rc : guard_check(p, st, grad_outputs(p, a));
   } catch (const std::exception& e) {
     set_error(e.what());
     return RTE_EINVAL;
@@ -1067,11 +1102,19 @@ int rte_batch_gradient(rte_batch* h, const void* const* mu_a, const void* const*
       b.key = key;
     }
     RTE_CHECK(hipGraphLaunch(b.gexec, st));
+    for (size_t i = 0; i < n; ++i)
+      if (int rc = guard_check(*b.plans[i], st, grad_outputs(*b.plans[i], args[i]))) return rc;
     return RTE_OK;
   } catch (const std::exception& e) {
     set_error(e.what());
     return RTE_EINVAL;
   }
+}
+
+int rte_plan_set_guard(rte_plan* h, int enable) {
+  if (!nonnull(h, "plan")) return RTE_EINVAL;
+  reinterpret_cast<Plan*>(h)->guard = enable != 0;
+  return RTE_OK;
 }
 
 int rte_profile_enable(rte_plan* h, int enable) {

@@ -767,6 +767,22 @@ __global__ void flux_map_kernel(const T* __restrict__ st, double* __restrict__ o
   out[(int64_t)q * out_q_stride + (int64_t)j * nx + i] = dth * acc;
 }
 
+// Non-finite scan: every lane that meets a NaN or an infinity stores 1 (all
+// writers store the same value, so no atomics are needed).
+__global__ void nonfinite_kernel(const double* __restrict__ x, int64_t n, unsigned long long* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[t]);
+  if (bad) flag[0] = 1ull;
+}
+
+hipError_t launch_nonfinite(const double* x, int64_t n, unsigned long long* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(blocks), dim3(256), 0, s, x, n, flag);
+  return hipGetLastError();
+}
+
 // Zero fill and device copy as kernels (8-byte words): graph captures of the
 // step sequence then hold only kernel nodes.
 __global__ void fill_zero_kernel(unsigned long long* __restrict__ p, int64_t n) {

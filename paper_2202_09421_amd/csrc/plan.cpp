@@ -258,7 +258,7 @@ static bool validate(const rte_problem* p, const rte_beam* beams, int64_t nbm, c
 
 static void free_tables(DeviceTables& t) {
   void* ps[] = {t.xi, t.eta, t.Wt, t.bc, t.bct, t.kappa, t.det_w, t.beam_sp, t.beam_an, t.beam_tt, t.beam_off,
-                t.slot_m, t.fc_buf, t.det_sp, t.slot_rev};
+                t.slot_m, t.fc_buf, t.det_sp, t.slot_rev, t.guard_flag};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   t = DeviceTables();
@@ -508,7 +508,8 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
             upload(bct, &p.dev.bct) && upload(kappa, &p.dev.kappa) && upload(detw, &p.dev.det_w) &&
             upload(bsp, &p.dev.beam_sp) && upload(ban, &p.dev.beam_an) && upload(btt, &p.dev.beam_tt) &&
             upload(boff, &p.dev.beam_off) && upload(slotm, &p.dev.slot_m) && upload(fcbuf, &p.dev.fc_buf) &&
-            upload(detsp, &p.dev.det_sp) && upload(srev, &p.dev.slot_rev);
+            upload(detsp, &p.dev.det_sp) && upload(srev, &p.dev.slot_rev) &&
+            upload(std::vector<unsigned long long>(1, 0ull), &p.dev.guard_flag);
   if (!ok) {
     set_error("device allocation or upload of the plan tables failed");
     free_tables(p.dev);

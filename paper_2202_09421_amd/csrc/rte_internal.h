@@ -81,6 +81,8 @@ struct DeviceTables {
   // boundary positions, and the slot of the reversed ordinate theta + pi
   double* det_sp = nullptr;    // [Nd][nb]
   int32_t* slot_rev = nullptr; // [Mpad] (padding slots map to themselves)
+  // non-finite guard flag (one 8-byte word, the only mutable plan memory)
+  unsigned long long* guard_flag = nullptr;
 };
 
 struct Plan {
@@ -110,6 +112,7 @@ struct Plan {
   int64_t saved_K = 0;
   // graph mode: rte_gradient recorded once per argument set, then replayed
   bool use_graph = false;
+  bool guard = false;          // scan outputs for NaN / Inf after each call
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
   const void* gkey[9] = {nullptr};
@@ -242,6 +245,8 @@ hipError_t launch_permute(const Plan& p, const void* in, void* state, hipStream_
 // scalar flux of the chunk's sources: out[q'][j][i] for q' = 0 .. cnq - 1 at
 // out + q' out_q_stride (the caller offsets out to the chunk's first source)
 hipError_t launch_flux_map(const Plan& p, const void* state, double* out, int64_t out_q_stride, hipStream_t s);
+// flag[0] = 1 if any of x[0 .. n) is NaN or infinite (flag left alone otherwise)
+hipError_t launch_nonfinite(const double* x, int64_t n, unsigned long long* flag, hipStream_t s);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
 hipError_t launch_copy(void* d, const void* src, int64_t bytes, hipStream_t s);
 

@@ -26,7 +26,7 @@ from .fc_tables import fc_tables
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librte.so")
 
-RTE_OK, RTE_EINVAL, RTE_ENOMEM, RTE_EDEVICE, RTE_EUNSUPPORTED, RTE_ESTATE = 0, -1, -2, -3, -5, -6
+RTE_OK, RTE_EINVAL, RTE_ENOMEM, RTE_EDEVICE, RTE_EUNSTABLE, RTE_EUNSUPPORTED, RTE_ESTATE = 0, -1, -2, -3, -4, -5, -6
 RTE_F64, RTE_F32 = 0, 1
 
 
@@ -101,6 +101,7 @@ def lib():
         L.rte_gradient_continuous.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
         L.rte_forward_ex.argtypes = [vp, vp, vp, ctypes.POINTER(rte_forward_extra), vp, vp, vp, i64, vp]
         L.rte_plan_set_graph.argtypes = [vp, ctypes.c_int]
+        L.rte_plan_set_guard.argtypes = [vp, ctypes.c_int]
         L.rte_batch_create.argtypes = [ctypes.POINTER(vp), i64, ctypes.POINTER(vp)]
         L.rte_batch_destroy.argtypes = [vp]
         pp = ctypes.POINTER(vp)
@@ -117,7 +118,7 @@ def lib():
                   "rte_adjoint", "rte_gradient", "rte_profile_enable", "rte_profile_read", "rte_plan_set_graph",
                   "rte_batch_create", "rte_batch_destroy", "rte_batch_gradient", "rte_plan_get_schedule",
                   "rte_plan_set_schedule", "rte_plan_autotune", "rte_plan_time_kernels", "rte_gradient_continuous",
-                  "rte_forward_ex"):
+                  "rte_forward_ex", "rte_plan_set_guard"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -309,6 +310,12 @@ class Plan:
         us = (ctypes.c_double * len(KERNEL_CLASSES))()
         _check(lib().rte_plan_time_kernels(self._h, _ptr(a), _ptr(b), _ptr(ws), ws.numel(), _stream(), int(reps), us))
         return {k: us[i] for i, k in enumerate(KERNEL_CLASSES)}
+
+    def set_guard(self, on=True):
+        """Non-finite guard (rte_plan_set_guard): every call then scans its
+        FP64 outputs after the solve, waits for the stream and raises RteError
+        with code RTE_EUNSTABLE if any value is NaN or infinite."""
+        _check(lib().rte_plan_set_guard(self._h, 1 if on else 0))
 
     def set_graph(self, on=True):
         """Graph mode: rte_gradient is recorded once per argument set and

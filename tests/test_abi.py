@@ -82,6 +82,7 @@ def test_null_arguments_are_errors():
     assert L.rte_forward(None, None, None, None, None, 0, None, 0, None) == rte.RTE_EINVAL
     assert "NULL" in L.rte_last_error().decode()
     assert L.rte_adjoint(None, None, None, None, None, None, None, 0, None) == rte.RTE_EINVAL
+    assert L.rte_plan_set_guard(None, 1) == rte.RTE_EINVAL
 
 
 def test_library_fc_tables_match_oracle():
