@@ -67,3 +67,20 @@ def test_guard_keeps_healthy_results(rte):
         got = [x.cpu().numpy() for x in plan.gradient(spec.mu_a, spec.mu_s, Gm)]
         for x, y in zip(got, ref):
             assert np.array_equal(x, y), graph
+
+
+def test_guard_in_a_batch(rte):
+    specs = [_spec(), W.small_problem(N=20, M=8, K=40, seed=9)]
+    plans = [rte.Plan(s, torch.float64) for s in specs]
+    for p in plans:
+        p.set_guard(True)
+    gms = [np.zeros((1, len(s.detectors), s.K)) for s in specs]
+    good = [(s.mu_a, s.mu_s) for s in specs]
+    batch = rte.Batch(plans)
+    J, _, _, _ = batch.gradient(good, gms)  # healthy: no error
+    assert all(np.isfinite(j.item()) for j in J)
+    bad_a = specs[1].mu_a.copy()
+    bad_a[3, 4] = np.inf
+    batch2 = rte.Batch(plans)
+    say("guard: batch with an Inf node in the second instance")
+    _unstable(rte, plans[1], lambda: batch2.gradient([good[0], (bad_a, specs[1].mu_s)], gms))
