@@ -281,3 +281,25 @@ def test_neck_phantom_first_steps(rte):
         say("  %s: u %.2e  G (max abs / state max) %.2e" % (dt, eu, eg))
         assert eu < bar and eg < bar
         plan.close()
+
+
+def test_mss_workload_first_steps(rte):
+    # the batched MSS workload's own grid (513 x 513 nodes, 64 ordinates,
+    # N_p = 540 four-step lines), two of its combinations solved together,
+    # the first 3 steps, FP64 and FP32 against the FP64 oracle
+    import dataclasses
+    full = W.config(2)
+    keep = {0: 0, 5: 1}
+    spec = full.with_(K=3, beams=[dataclasses.replace(b, group=keep[b.group]) for b in full.beams if b.group in keep])
+    say("mss first steps", spec.Nx + 1, spec.M, spec.Nq, spec.K)
+    G_o, uK_o, _ = Oracle(spec).forward()
+    scale = max(np.abs(G_o).max(), np.abs(uK_o).max())
+    for dt, bar in ((torch.float64, TOL64), (torch.float32, TOL32)):
+        plan = rte.Plan(spec, dt)
+        assert plan.Np_x == 540 and plan.Nq == 2
+        G, uK = plan.forward(spec.mu_a, spec.mu_s, want_u_final=True)
+        torch.cuda.synchronize()
+        eu, eg = rel(uK.cpu(), uK_o), np.abs(G.cpu().numpy() - G_o).max() / scale
+        say("  %s: u %.2e  G (max abs / state max) %.2e" % (dt, eu, eg))
+        assert eu < bar and eg < bar
+        plan.close()
