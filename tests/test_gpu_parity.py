@@ -303,3 +303,22 @@ def test_mss_workload_first_steps(rte):
         say("  %s: u %.2e  G (max abs / state max) %.2e" % (dt, eu, eg))
         assert eu < bar and eg < bar
         plan.close()
+
+
+@pytest.mark.parametrize("idx", [4, 9])
+def test_uneven_instances_first_steps(rte, idx):
+    # full-size instances of the uneven batch with 48 ordinates (3 row tiles
+    # of 16 slots) on their own grids (330 and 481 nodes per side: N_p = 360
+    # and 512), the first 3 steps, FP64 and FP32 against the FP64 oracle
+    spec = W.uneven_batch()[idx].with_(K=3)
+    say("uneven instance", idx, spec.Nx + 1, spec.M)
+    G_o, uK_o, _ = Oracle(spec).forward()
+    scale = max(np.abs(G_o).max(), np.abs(uK_o).max())
+    for dt, bar in ((torch.float64, TOL64), (torch.float32, TOL32)):
+        plan = rte.Plan(spec, dt)
+        G, uK = plan.forward(spec.mu_a, spec.mu_s, want_u_final=True)
+        torch.cuda.synchronize()
+        eu, eg = rel(uK.cpu(), uK_o), np.abs(G.cpu().numpy() - G_o).max() / scale
+        say("  %s: N_p %d, u %.2e  G (max abs / state max) %.2e" % (dt, plan.Np_x, eu, eg))
+        assert eu < bar and eg < bar
+        plan.close()
