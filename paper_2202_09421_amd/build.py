@@ -57,5 +57,38 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_host_sanitized(out_dir: str) -> str:
+    """The library with its host code (plan.cpp, capi.cpp) built under
+    AddressSanitizer and UndefinedBehaviorSanitizer, linked with the kernel
+    objects of the last build(); for CPU tests of the table construction and
+    argument checks (load it with the ASan runtime preloaded).  Returns the
+    path of the shared library."""
+    os.makedirs(out_dir, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer"]
+    objs = []
+    for src in SOURCES:
+        if src.endswith(".cpp"):
+            obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+            cmd = [_hipcc(), "-x", "hip", "-O1", "-g", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+                   "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"] + san + \
+                  ["-I", os.path.join(HERE, "..", "include"), "-c", os.path.join(CSRC, src), "-o", obj]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stderr))
+        else:
+            obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+            if not os.path.exists(obj):
+                raise RuntimeError("kernel object %s missing: run build() first" % obj)
+        objs.append(obj)
+    lib = os.path.join(out_dir, "librte_hostsan.so")
+    cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", "-o", lib] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stderr))
+    return lib
+
+
 if __name__ == "__main__":
     build(verbose=True)
