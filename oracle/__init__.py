@@ -17,6 +17,11 @@ Modules
               beams and detectors (Sec. 2, 3.1, 4.1)
   solver   -- AB4 forward solve, misfit, exact discrete adjoint and gradient
               (Sec. 3.2-3.6, 4.2, Algorithm 1)
+  cadjoint -- the continuous adjoint problem solved as a reversed forward
+              problem, and its gradient (Sec. 3.3-3.6, eqs. AdjointProblem,
+              FDwin22)
+  mms      -- the manufactured-solution problem: exact solution, source and
+              start-up history (Sec. 5, eqs. RTEdisp, RTEmansol)
 
 Every function states the passage it follows.  "parity unpinned" marks the
 readings the paper leaves open and nothing outside the oracle can confirm:
