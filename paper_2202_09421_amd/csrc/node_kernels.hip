@@ -51,16 +51,21 @@ struct Mfma<float> {
 
 // Tiling.  A wave owns a 16-node tile (16 consecutive positions of the
 // row-padded layout) and one row tile of 16 output slots (4 ordinate groups);
-// lane l holds node l % 16, slot r = l / 16 of each of its 4 groups, so every
-// global access of a wave is a contiguous 512-byte run per group.  The
-// scattering D[s][node] = sum_s' Wt[s'][s] X[s'][node] is a 16 x 16 x Mpad
+// lane l holds 4 values of node l % 16 (which 4: see the lane maps below).
+// The scattering D[s][node] = sum_s' Wt[s'][s] X[s'][node] is a 16 x 16 x Mpad
 // MFMA product per wave: the A operand is the wave's slice of the HG matrix
 // (kept in registers), the B operand (X at all slots of the tile) is
 // exchanged through LDS among the RT waves that share the tile, and the
 // result lands in exactly the (node, slot) registers of the lane that owns
-// it (for FP32 the rows of the A operand are permuted to make it so).
-// Boundary coupling only mixes slots of one group (the groups are
-// reflection orbits), i.e. the 4 lanes of one node, and uses wave shuffles.
+// it.  Boundary coupling only mixes slots of one group (the groups are
+// reflection orbits).
+// Lane maps.  FP64: lane (node, r) holds slot r of the 4 groups of its row
+// tile (the FP64 MFMA returns rows r, r + 4, r + 8, r + 12 to lane r), so
+// every access is a 512-byte run of 8-byte lanes and the boundary coupling
+// uses wave shuffles among the 4 lanes of a node.  FP32 ("vector lanes"):
+// lane (node, r) holds the 4 slots of group r of its row tile (the FP32 MFMA
+// returns rows 4r .. 4r + 3 to lane r), so each array is one 16-byte load
+// per lane and the boundary coupling stays in the lane's registers.
 // NT tiles x RT row tiles per block; RTC = RT at compile time (1..4) or 0
 // for RT >= 5 (NT = 1).
 struct NodeGeom {
@@ -84,8 +89,12 @@ __device__ __forceinline__ int boundary_pos(int j, int i, int nx, int ny) {
 }
 
 template <typename T>
-__device__ __forceinline__ int a_row_slot(int rho) {
-  return sizeof(T) == 8 ? rho : 4 * (rho & 3) + (rho >> 2);
+constexpr bool kVecLane = sizeof(T) == 4;
+
+// slot (ordinate storage index) of value v of the lane
+template <typename T, typename TL>
+__device__ __forceinline__ int lane_slot(const TL& t, int v) {
+  return kVecLane<T> ? 4 * (4 * t.rt + t.r) + v : 4 * (4 * t.rt + v) + t.r;
 }
 
 struct TileLane {
@@ -123,7 +132,7 @@ __device__ __forceinline__ typename Mfma<T>::acc_t scatter_tile(const T* Bs, con
 #pragma unroll
     for (int ks = 0; ks < 4 * RTC; ++ks) acc = Mfma<T>::step(af[ks], Bs[(4 * ks + t.r) * 16 + t.node], acc);
   } else {
-    const int col = 16 * t.rt + a_row_slot<T>(t.node);
+    const int col = 16 * t.rt + t.node;
     for (int ks = 0; ks < 4 * G.RT; ++ks)
       acc = Mfma<T>::step(T(Wt[(4 * ks + t.r) * G.Mpad + col]), Bs[(4 * ks + t.r) * 16 + t.node], acc);
   }
@@ -142,10 +151,61 @@ __device__ __forceinline__ void sto(T* base, uint32_t boff, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
 }
 
+// The lane's 4 values of one array: per-value offsets off[v] (FP64) or one
+// 16-byte vector at off[0] (FP32); ok[v] masks the values.
+template <typename T>
+__device__ __forceinline__ void ld4(const T* base, const uint32_t* off, const bool* ok, T* x) {
+  if constexpr (kVecLane<T>) {
+    float4 q = {0.f, 0.f, 0.f, 0.f};
+    if (ok[0]) q = ldo(reinterpret_cast<const float4*>(base), off[0]);
+    x[0] = q.x; x[1] = q.y; x[2] = q.z; x[3] = q.w;
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = ok[v] ? ldo(base, off[v]) : T(0);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void st4(T* base, const uint32_t* off, const bool* ok, const T* x) {
+  if constexpr (kVecLane<T>) {
+    if (ok[0]) sto(reinterpret_cast<float4*>(base), off[0], make_float4(x[0], x[1], x[2], x[3]));
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (ok[v]) sto(base, off[v], x[v]);
+  }
+}
+// Lane offsets and masks of the 4 values.
+template <typename T>
+__device__ __forceinline__ void lane_offsets(const NodeGeom& G, const TileLane& t, uint32_t* off, bool* ok) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int s = lane_slot<T>(t, v);
+    ok[v] = t.valid && (s >> 2) < G.G;
+    off[v] = (uint32_t)(((uint32_t)(s >> 2) * (uint32_t)G.grp_stride + (uint32_t)t.P * kGroup + (s & 3)) * sizeof(T));
+  }
+}
+// Byte offset of the value at the reversed ordinate of the lane's value v
+// (same node): the paired forward state of the continuous adjoint.
+template <typename T>
+__device__ __forceinline__ uint32_t pair_offset(const NodeGeom& G, const TileLane& t, const int32_t* slot_rev, int v) {
+  const int sr = slot_rev[lane_slot<T>(t, v)];
+  return (uint32_t)(((uint32_t)(sr >> 2) * (uint32_t)G.grp_stride + (uint32_t)t.P * kGroup + (sr & 3)) * sizeof(T));
+}
+// Value of slot c (0..3) of the group that holds the lane's value v, for the
+// same node: another lane's register (FP64) or one of the lane's own (FP32).
+template <typename T>
+__device__ __forceinline__ T group_peer(const T* x, int v, int c, const TileLane& t) {
+  if constexpr (kVecLane<T>) {
+    return c == 0 ? x[0] : (c == 1 ? x[1] : (c == 2 ? x[2] : x[3]));
+  } else {
+    return __shfl(x[v], t.node + 16 * c);
+  }
+}
+
 template <typename T, int RTC>
 __device__ __forceinline__ void load_afrag(T* af, const double* __restrict__ Wt, const NodeGeom& G, const TileLane& t) {
   if constexpr (RTC > 0) {
-    const int col = 16 * t.rt + a_row_slot<T>(t.node);
+    const int col = 16 * t.rt + t.node;
 #pragma unroll
     for (int ks = 0; ks < 4 * RTC; ++ks) af[ks] = T(Wt[(4 * ks + t.r) * G.Mpad + col]);
   }
@@ -213,20 +273,33 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
   T u[4], X[4], Y[4], L1[4], L2[4], L3[4], up[4];
   uint32_t off[4];
   bool gv[4];
+  lane_offsets<T>(G, t, off, gv);
+  if constexpr (kVecLane<T>) {
+    ld4(uq, off, gv, u);
+    ld4(Xq, off, gv, X);
+    ld4(Yq, off, gv, Y);
+    ld4(L1q, off, gv, L1);
+    ld4(L2q, off, gv, L2);
+    ld4(L3q, off, gv, L3);
+  } else {
+    // value by value, all arrays of one value together (this issue order
+    // streams measurably faster than array by array)
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int g = 4 * t.rt + v;
-    gv[v] = t.valid && g < G.G;
-    off[v] = (uint32_t)(((uint32_t)g * (uint32_t)G.grp_stride + (uint32_t)t.P * kGroup + t.r) * sizeof(T));
-    u[v] = X[v] = Y[v] = L1[v] = L2[v] = L3[v] = up[v] = T(0);
-    if (gv[v]) {
-      u[v] = ldo(uq, off[v]); X[v] = ldo(Xq, off[v]); Y[v] = ldo(Yq, off[v]);
-      L1[v] = ldo(L1q, off[v]); L2[v] = ldo(L2q, off[v]); L3[v] = ldo(L3q, off[v]);
+    for (int v = 0; v < 4; ++v) {
+      u[v] = X[v] = Y[v] = L1[v] = L2[v] = L3[v] = up[v] = T(0);
+      if (gv[v]) {
+        u[v] = ldo(uq, off[v]); X[v] = ldo(Xq, off[v]); Y[v] = ldo(Yq, off[v]);
+        L1[v] = ldo(L1q, off[v]); L2[v] = ldo(L2q, off[v]); L3[v] = ldo(L3q, off[v]);
+        if constexpr (CADJ) up[v] = ldo(a.upair + ib, pair_offset<T>(G, t, a.slot_rev, v));
+      }
+    }
+  }
+  if constexpr (kVecLane<T>) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      up[v] = T(0);
       if constexpr (CADJ) {
-        const int sr = a.slot_rev[4 * g + t.r];
-        const uint32_t offr =
-            (uint32_t)(((uint32_t)(sr >> 2) * (uint32_t)G.grp_stride + (uint32_t)t.P * kGroup + (sr & 3)) * sizeof(T));
-        up[v] = ldo(a.upair + ib, offr);
+        if (gv[v]) up[v] = ldo(a.upair + ib, pair_offset<T>(G, t, a.slot_rev, v));
       }
     }
   }
@@ -236,7 +309,7 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
   load_afrag<T, RTC>(af, a.Wt, G, t);
 
 #pragma unroll
-  for (int v = 0; v < 4; ++v) Bs[(4 * (4 * t.rt + v) + t.r) * 16 + t.node] = u[v];
+  for (int v = 0; v < 4; ++v) Bs[lane_slot<T>(t, v) * 16 + t.node] = u[v];
   __syncthreads();
   const typename Mfma<T>::acc_t S = scatter_tile<T, RTC>(Bs, af, a.Wt, G, t);
 
@@ -248,18 +321,20 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         if (gv[v])
-          qv[v] = T(sep_value(a.vsrc, a.step + 3, G.K1 + 3, t.i, t.j, G.nx, G.ny, G.M,
-                              a.slot_m[4 * (4 * t.rt + v) + t.r]));
+          qv[v] = T(sep_value(a.vsrc, a.step + 3, G.K1 + 3, t.i, t.j, G.nx, G.ny, G.M, a.slot_m[lane_slot<T>(t, v)]));
     }
   }
-  T un[4];
+  T un[4], Ln[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    T Ln = B * S[v] - (A + B) * u[v] + X[v] + Y[v];
-    if constexpr (EXT) Ln += qv[v];
-    un[v] = u[v] + cdt * (T(kChi0) * Ln + T(kChi1) * L1[v] + T(kChi2) * L2[v] + T(kChi3) * L3[v]);
-    if (gv[v]) sto(Loq, off[v], Ln);
+    Ln[v] = B * S[v] - (A + B) * u[v] + X[v] + Y[v];
+    if constexpr (EXT) Ln[v] += qv[v];
+    un[v] = u[v] + cdt * (T(kChi0) * Ln[v] + T(kChi1) * L1[v] + T(kChi2) * L2[v] + T(kChi3) * L3[v]);
+    if constexpr (!kVecLane<T>) {
+      if (gv[v]) sto(Loq, off[v], Ln[v]);
+    }
   }
+  if constexpr (kVecLane<T>) st4(Loq, off, gv, Ln);
 
   // inflow condition with Fresnel reflection and the beams at t_{n+1}.  The
   // boundary tables (reflection rules, beam factors, detector weights) of the
@@ -277,7 +352,7 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
     const int b0 = a.beam_off[q], b1 = a.beam_off[q + 1];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int s = 4 * (4 * t.rt + v) + t.r;
+      const int s = lane_slot<T>(t, v);
       const bool on = t.bnd && gv[v];
       br[v].flag = 0; br[v].src_a = s; br[v].src_b = s; br[v].pad = 0; br[v].coef_a = 0.0; br[v].coef_b = 0.0;
       if (on) br[v] = a.bc[ty * G.M + s];
@@ -297,10 +372,11 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
       k0[v] = (on && a.flux && wl0 >= 0) ? a.kappa[wl0 * G.M + s] : 0.0;
       k1[v] = (on && a.flux && wl1 >= 0) ? a.kappa[wl1 * G.M + s] : 0.0;
     }
+    const T uc[4] = {un[0], un[1], un[2], un[3]};
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const T ta = __shfl(un[v], t.node + 16 * (br[v].src_a & 3));
-      const T tb = __shfl(un[v], t.node + 16 * (br[v].src_b & 3));
+      const T ta = group_peer(uc, v, br[v].src_a & 3, t);
+      const T tb = group_peer(uc, v, br[v].src_b & 3, t);
       if (br[v].flag) un[v] = T(br[v].coef_a) * ta + T(br[v].coef_b) * tb + src[v];
     }
     // detector flux on boundary nodes (FP64): lane partial over its 4
@@ -315,9 +391,7 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
     pw0 += __shfl_xor(pw0, 32);
     pw1 += __shfl_xor(pw1, 32);
   }
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-    if (gv[v]) sto(uoq, off[v], un[v]);
+  st4(uoq, off, gv, un);
 
   if constexpr (CADJ) {
     double pa = 0.0, pb = 0.0;
@@ -409,16 +483,24 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
   T tx[4], ty[4], p1[4], v2[4], v3[4], v4[4], uu[4];
   uint32_t off[4];
   bool gv[4];
+  lane_offsets<T>(G, t, off, gv);
+  if constexpr (kVecLane<T>) {
+    ld4(txq, off, gv, tx);
+    ld4(tyq, off, gv, ty);
+    ld4(static_cast<const T*>(p1q), off, gv, p1);
+    ld4(v2q, off, gv, v2);
+    ld4(v3q, off, gv, v3);
+    ld4(v4q, off, gv, v4);
+    ld4(uq, off, gv, uu);
+  } else {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int g = 4 * t.rt + v;
-    gv[v] = t.valid && g < G.G;
-    off[v] = (uint32_t)(((uint32_t)g * (uint32_t)G.grp_stride + (uint32_t)t.P * kGroup + t.r) * sizeof(T));
-    tx[v] = ty[v] = p1[v] = v2[v] = v3[v] = v4[v] = uu[v] = T(0);
-    if (gv[v]) {
-      tx[v] = ldo(txq, off[v]); ty[v] = ldo(tyq, off[v]); p1[v] = ldo(p1q, off[v]);
-      v2[v] = ldo(v2q, off[v]); v3[v] = ldo(v3q, off[v]); v4[v] = ldo(v4q, off[v]);
-      uu[v] = ldo(uq, off[v]);
+    for (int v = 0; v < 4; ++v) {
+      tx[v] = ty[v] = p1[v] = v2[v] = v3[v] = v4[v] = uu[v] = T(0);
+      if (gv[v]) {
+        tx[v] = ldo(txq, off[v]); ty[v] = ldo(tyq, off[v]); p1[v] = ldo(p1q, off[v]);
+        v2[v] = ldo(v2q, off[v]); v3[v] = ldo(v3q, off[v]); v4[v] = ldo(v4q, off[v]);
+        uu[v] = ldo(uq, off[v]);
+      }
     }
   }
   const int gn = t.j * G.nx + t.i;
@@ -445,7 +527,7 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
     BcRuleT rt[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int s = 4 * (4 * t.rt + v) + t.r;
+      const int s = lane_slot<T>(t, v);
       const bool on = t.bnd && gv[v];
       rt[v].is_target = 0; rt[v].ntgt = 0; rt[v].tgt[0] = s; rt[v].tgt[1] = s; rt[v].coef[0] = 0.0; rt[v].coef[1] = 0.0;
       if (on) rt[v] = a.bct[tyn * G.M + s];
@@ -459,10 +541,11 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
         injv[v] = p;
       }
     }
+    const T vc[4] = {v1[0], v1[1], v1[2], v1[3]};
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const T t0 = __shfl(v1[v], t.node + 16 * (rt[v].tgt[0] & 3));
-      const T t1 = __shfl(v1[v], t.node + 16 * (rt[v].tgt[1] & 3));
+      const T t0 = group_peer(vc, v, rt[v].tgt[0] & 3, t);
+      const T t1 = group_peer(vc, v, rt[v].tgt[1] & 3, t);
       if (t.bnd && gv[v]) {
         T val = rt[v].is_target ? T(0) : v1[v];
         if (rt[v].ntgt > 0) val += T(rt[v].coef[0]) * t0;
@@ -477,7 +560,7 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     w[v] = T(kChi0) * v1[v] + T(kChi1) * v2[v] + T(kChi2) * v3[v] + T(kChi3) * v4[v];
-    Bs[(4 * (4 * t.rt + v) + t.r) * 16 + t.node] = w[v];
+    Bs[lane_slot<T>(t, v) * 16 + t.node] = w[v];
   }
   __syncthreads();
   const typename Mfma<T>::acc_t S = scatter_tile<T, RTC>(Bs, af, a.Wt, G, t);
@@ -485,16 +568,24 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
   // P1^n, stores and the gradient products
   const T cdtT = T(cdt);
   double pa = 0.0, pb = 0.0;
+  T pn[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const T p = v1[v] + cdtT * (B * S[v] - (A + B) * w[v]) + injv[v];
-    if (gv[v]) {
-      sto(p1q, off[v], p);
-      sto(wq, off[v], w[v]);
-      sto(v1q, off[v], v1[v]);
+    pn[v] = v1[v] + cdtT * (B * S[v] - (A + B) * w[v]) + injv[v];
+    if constexpr (!kVecLane<T>) {
+      if (gv[v]) {
+        sto(p1q, off[v], pn[v]);
+        sto(wq, off[v], w[v]);
+        sto(v1q, off[v], v1[v]);
+      }
     }
     pa += (double)uu[v] * (double)w[v];
     pb += (double)uu[v] * ((double)S[v] - (double)w[v]);
+  }
+  if constexpr (kVecLane<T>) {
+    st4(p1q, off, gv, pn);
+    st4(wq, off, gv, w);
+    st4(v1q, off, gv, v1);
   }
   pa += __shfl_xor(pa, 16);
   pb += __shfl_xor(pb, 16);
