@@ -176,8 +176,11 @@ def test_checkpointed_replay_is_bitwise_equal(rte):
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("case", [CASES[1], CASES[5]], ids=["16", "64"])
+@pytest.mark.parametrize("case", [CASES[1], CASES[5], CASES[7], CASES[9], CASES[2]], ids=["16", "64", "48", "80", "13"])
 def test_fp32_matches_fp64_oracle(rte, case):
+    # FP32 node passes use vector lanes (4 slots of one group per lane): 1 to
+    # 4 row tiles of 16 slots at compile time and 5 at run time, square and
+    # rectangular grids, Fresnel and index-matched boundaries
     spec = _spec(case)
     say("fp32", case)
     o = Oracle(spec)
