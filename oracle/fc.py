@@ -21,12 +21,36 @@ For even N_p the k = N_p/2 coefficient of the derivative is set to zero
 complex).  The derivative at the n grid nodes is the first n entries.
 
 The FFT is numpy's (a library primitive); everything else is written out.
+set_fft_workers(n) switches it to scipy's (the same pocketfft algorithm) with
+n threads, for timing the oracle on every host core.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from .fc_gram import blend_table
+
+_FFT_WORKERS = None
+
+
+def set_fft_workers(n):
+    """None: numpy.fft (one thread).  n >= 1: scipy.fft with n worker threads."""
+    global _FFT_WORKERS
+    _FFT_WORKERS = n
+
+
+def _fft(x):
+    if _FFT_WORKERS is None:
+        return np.fft.fft(x, axis=-1)
+    import scipy.fft
+    return scipy.fft.fft(x, axis=-1, workers=_FFT_WORKERS)
+
+
+def _ifft(x):
+    if _FFT_WORKERS is None:
+        return np.fft.ifft(x, axis=-1)
+    import scipy.fft
+    return scipy.fft.ifft(x, axis=-1, workers=_FFT_WORKERS)
 
 
 def is_5smooth(n: int) -> bool:
@@ -79,7 +103,7 @@ class FCLine:
         return np.concatenate([g, ext], axis=-1)
 
     def periodic_derivative(self, gc: np.ndarray) -> np.ndarray:
-        return np.fft.ifft(self.lam * np.fft.fft(gc, axis=-1), axis=-1).real
+        return _ifft(self.lam * _fft(gc)).real
 
     def derivative(self, g: np.ndarray, axis: int = -1) -> np.ndarray:
         g = np.moveaxis(np.asarray(g, dtype=np.float64), axis, -1)
@@ -93,7 +117,7 @@ class FCLine:
         z = np.zeros(y.shape[:-1] + (Np,))
         z[..., :n] = y                                            # transpose of "first n entries"
         # transpose of the real circulant: conjugate multiplier
-        z = np.fft.ifft(np.conj(self.lam) * np.fft.fft(z, axis=-1), axis=-1).real
+        z = _ifft(np.conj(self.lam) * _fft(z)).real
         g = z[..., :n].copy()                                     # transpose of [g; ext]
         zext = z[..., n:]
         g[..., n - d:] += zext[..., :C] @ self.B.T                # transpose of the right blend

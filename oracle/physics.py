@@ -21,7 +21,9 @@ Readings where the paper is silent:
   * Corners: an ordinate incoming through both walls of a corner follows the
     wall with the larger |theta.nu|; on an exact tie the two walls' reflection
     terms are averaged.  Tangential ordinates (theta.nu = 0) get no condition.
-  * Source time profile: exp(-(t - tau - t0)^2 / (2 sigma_t^2)).
+  * Source time profile: exp(-(t - tau - t0)^2 / (2 sigma_t^2)), or, for a
+    beam whose profile is "window", the window of eq. (sourcelabwind) in
+    |t - t_s| / sigma_t with t_s = tau + t0 (eq. sourcelab).
   * Detector quadrature: trapezoid along each wall (half weight at the two end
     nodes of a wall), DOM sum over strictly outgoing ordinates.
 Signs of theta.nu are decided with integer arithmetic on m so that the
@@ -210,7 +212,12 @@ def beam_spatial_angular(beam, xb, yb, theta_m):
 
 
 def beam_time(beam, t):
-    return np.exp(-((t - beam.tau - beam.t0) ** 2) / (2.0 * beam.sigma_t ** 2))
+    """Temporal factor T(t - tau) of eq. (RTEsources2): a Gaussian, or the
+    window w(|t - t_s| / sigma_t) of eq. (sourcelab)."""
+    s = t - beam.tau - beam.t0
+    if getattr(beam, "profile", "gauss") == "window":
+        return window(s / beam.sigma_t)
+    return np.exp(-(s ** 2) / (2.0 * beam.sigma_t ** 2))
 
 
 # ------------------------------------------------------------------ detectors

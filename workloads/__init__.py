@@ -41,6 +41,7 @@ class Beam:
     sigma_t: float = 20.0  # ps
     t0: float = 60.0      # ps, pulse centre offset (3 sigma_t) so q(t<=0) ~ 0
     group: int = 0        # generalised source index i of q_i
+    profile: str = "gauss"  # temporal profile: "gauss" or "window" (eq. sourcelab)
 
 
 @dataclasses.dataclass
@@ -345,8 +346,9 @@ def inverse_phantom(mode: str = "mss", N: int = 64, M: int = 16, seed: int = 6, 
 def lab_flux(N: int = 200, M: int = 32, times=(30.0, 100.0, 170.0), dt: Optional[float] = None):
     """The laboratory photon-flux simulation of Sec. 5 (Fig. 6): [0,3]^2 cm,
     homogeneous a = 0.35 /cm, b = 20 /cm, g = 0.8, n = 1.4, one beam at
-    (1.5, 0) along the inward normal (sigma_x = 0.3 cm, sigma_theta = pi/4,
-    pulse centred at t = 0 with sigma_t = 30 ps).  Returns (spec, steps):
+    (1.5, 0) along the inward normal (sigma_x = 0.3 cm, sigma_theta = pi/4)
+    with the window time profile of eq. (sourcelab), t_s = 0 and
+    sigma_t = 30 ps, as printed.  Returns (spec, steps):
     K reaches the last snapshot time and steps[k] is the time level nearest
     times[k]."""
     L = 3.0
@@ -357,7 +359,8 @@ def lab_flux(N: int = 200, M: int = 32, times=(30.0, 100.0, 170.0), dt: Optional
         dt = default_dt(h, h, C_LIGHT, a, b)
     steps = [int(round(t / dt)) for t in times]
     spec = ProblemSpec(0, L, 0, L, N, N, M, max(steps), dt, a, b,
-                       [beam_at(1.5, 0.0, 0, L, 0, L, sigma_t=30.0, t0=0.0)], perimeter_detectors(4, 0, L, 0, L),
+                       [beam_at(1.5, 0.0, 0, L, 0, L, sigma_t=30.0, t0=0.0, profile="window")],
+                       perimeter_detectors(4, 0, L, 0, L),
                        g=0.8, n_in=1.4, name="lab-flux-%dx%d-M%d" % (N, N, M))
     return spec, steps
 
