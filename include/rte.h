@@ -74,9 +74,13 @@ typedef struct {
   int64_t fc_d, fc_C;       /* matching points d and blend length C (Sec. 4.3)     */
   double filt_alpha, filt_beta; /* filter exp(-alpha |2k/Np|^(2 beta)), eq. (FFilter) */
   const double* fc_Q;       /* host, d*d row-major: Q[k*d+j] = P_j(k), the Gram
-                               basis on the d matching points                     */
+                               basis on the d matching points; NULL (with fc_A
+                               NULL): the built-in table, available for
+                               (fc_d, fc_C) = (5, 25), RTE_EUNSUPPORTED for
+                               other sizes                                        */
   const double* fc_A;       /* host, C*d row-major: A[p*d+j] = blend of P_j at the
-                               p-th continuation point (Sec. 4.3 step 2)          */
+                               p-th continuation point (Sec. 4.3 step 2); NULL
+                               together with fc_Q                                 */
   int64_t ckpt_every;       /* 0: keep every state u^0..u^K for the adjoint;
                                s > 0: keep checkpoints every s steps and replay
                                segments of s steps during the adjoint              */
@@ -89,15 +93,23 @@ typedef struct {
                                last one rte_forward left in the workspace.       */
 } rte_problem;
 
+/* Temporal profile T of a beam (eq. RTEsources2 leaves it general). */
+typedef enum {
+  RTE_PROFILE_GAUSSIAN = 0, /* exp(-(t - tau - t0)^2 / (2 sigma_t^2))                  */
+  RTE_PROFILE_WINDOW = 1    /* w(|t - tau - t0| / sigma_t), the window of
+                               eq. (sourcelabwind) as in eq. (sourcelab), t_s = tau+t0 */
+} rte_profile;
+
 /* A laser beam, eq. (RTEsources2)/(sourcelab):
  *   s(x, theta, t) = exp(-|x - (x,y)|^2 / (2 sigma_x^2))
- *                  * w(d(theta, theta_b) / sigma_theta) * exp(-(t - tau - t0)^2 / (2 sigma_t^2))
- * with w the window of eq. (sourcelabwind) and d the circular angular distance.
- * It enters through the inflow condition on the boundary.                    */
+ *                  * w(d(theta, theta_b) / sigma_theta) * T(t)
+ * with w the window of eq. (sourcelabwind), d the circular angular distance
+ * and T the temporal profile selected by `profile`.  It enters through the
+ * inflow condition on the boundary.                                         */
 typedef struct {
   double x, y, theta, sigma_x, sigma_theta, tau, sigma_t, t0;
   int32_t group;            /* generalised source q (0..Nq-1) this beam fires in */
-  int32_t reserved0;
+  int32_t profile;          /* rte_profile; RTE_EINVAL for other values          */
 } rte_beam;
 
 /* A detector, eq. (OpMed): boundary point and footprint sigma_d (cm). */
@@ -122,7 +134,10 @@ int rte_plan_info(const rte_plan* plan, int64_t* Nq, int64_t* Nd, int64_t* Np_x,
 
 /* Bytes of device workspace needed by rte_forward (+ rte_adjoint when
  * with_adjoint != 0).  The workspace carries the stored states between a
- * forward and its adjoint, so the same buffer must be passed to both.     */
+ * forward and its adjoint, so the same buffer must be passed to both.  Every
+ * call that takes a workspace requires its base address to be 256-byte
+ * aligned (RTE_EINVAL otherwise, before any device work); hipMalloc and
+ * torch allocations are.                                                   */
 int rte_workspace_bytes(const rte_plan* plan, int with_adjoint, int64_t* bytes);
 
 /* Forward solve, Algorithm 1 for all Nq sources.
@@ -139,7 +154,12 @@ int rte_forward(rte_plan* plan, const void* mu_a, const void* mu_s, double* G, v
  *   G_bar      : device, double [Nq][Nd][K], the cotangent dJ/dG
  *   dmu_a/dmu_s: device out, double [Ny+1][Nx+1]: dJ/da_ij, dJ/db_ij summed over
  *                the Nq sources (discrete eq. (FDwin22) and its b analogue).
- * RTE_ESTATE if no saved forward is in the workspace.                      */
+ * RTE_ESTATE if no saved forward is in the workspace: none was made, a later
+ * call on the plan overwrote it (rte_forward without saving, rte_forward_ex,
+ * rte_plan_autotune, rte_plan_time_kernels), or `workspace` is not the buffer
+ * the saving call (rte_forward, rte_gradient, rte_gradient_continuous, a
+ * batch gradient) used.  The medium must be the one of that call (not
+ * checked).                                                                */
 int rte_adjoint(rte_plan* plan, const void* mu_a, const void* mu_s, const double* G_bar,
                 double* dmu_a, double* dmu_s, void* workspace, int64_t workspace_bytes, void* stream);
 
@@ -152,6 +172,27 @@ int rte_adjoint(rte_plan* plan, const void* mu_a, const void* mu_s, const double
 int rte_gradient(rte_plan* plan, const void* mu_a, const void* mu_s, const double* G_meas,
                  double* J, double* dmu_a, double* dmu_s, double* G, void* workspace,
                  int64_t workspace_bytes, void* stream);
+
+/* Staged gradient.  rte_gradient enqueues a fixed sequence of n_ops
+ * operations (rte_gradient_ops): one that zeroes the accumulators; per
+ * combination chunk the forward start, K forward steps, the misfit, the
+ * adjoint start and then K adjoint steps (every state kept) or, per
+ * checkpoint segment from the last, the checkpoint restore, the replayed
+ * forward steps and the adjoint steps; and a final reduction of the gradient
+ * over the sources.  rte_gradient_range enqueues the operations with index
+ * in [first, last), with the arguments of rte_gradient.  The ranges of one
+ * gradient must be enqueued in order from first = 0 with identical
+ * arguments (RTE_ESTATE otherwise); consecutive ranges that cover
+ * [0, n_ops) compute exactly what one rte_gradient call computes, bit for
+ * bit.  J, dmu_a, dmu_s and G are complete once the range holding the last
+ * operation has run; the guard (if enabled) checks them then.  For
+ * long solves that must be interleaved with other work, bounded in time per
+ * call, or progress-reported.  Always eager (graph mode does not apply).
+ * RTE_EINVAL for a range outside [0, n_ops].                               */
+int rte_gradient_ops(const rte_plan* plan, int64_t* n_ops);
+int rte_gradient_range(rte_plan* plan, const void* mu_a, const void* mu_s, const double* G_meas, double* J,
+                       double* dmu_a, double* dmu_s, double* G, void* workspace, int64_t workspace_bytes,
+                       int64_t first, int64_t last, void* stream);
 
 /* A space-time-angle field given as a sum of separable products
  *   f(x_i, y_j, theta_m, t_n) = sum_k X[k][n+3][i] * Y[k][n+3][j] * Th[k][m]

@@ -131,90 +131,143 @@ void reset_chunk(const Plan& p) {
   p.cnq = p.chunk;
 }
 
-bool map_or_fail(const Plan& p, void* wsp, int64_t wsb, bool adj, Workspace* ws) {
-  if (map_workspace(p, wsp, wsb, adj, ws)) return true;
+// The workspace now holds the saved forward of every source; the states of
+// the last chunk are resident.
+void mark_saved(Plan& p, const void* wsp) {
+  p.have_forward = true;
+  p.saved_chunk = n_chunks(p) - 1;
+  p.saved_K = p.K;
+  p.saved_ws = wsp;
+}
+
+// Maps the workspace; RTE_EINVAL for a base that is not 256-byte aligned
+// (the kernels issue 16-byte vector accesses at offsets that are multiples
+// of 256 from it), RTE_ENOMEM for a buffer that is too small.
+int map_or_fail(const Plan& p, void* wsp, int64_t wsb, bool adj, Workspace* ws) {
+  if (reinterpret_cast<uintptr_t>(wsp) % 256 != 0) {
+    set_error("workspace must be 256-byte aligned");
+    return RTE_EINVAL;
+  }
+  if (map_workspace(p, wsp, wsb, adj, ws)) return RTE_OK;
   std::ostringstream o;
   o << "workspace too small: need " << workspace_bytes(p, adj) << " bytes";
   set_error(o.str());
-  return false;
+  return RTE_ENOMEM;
+}
+
+// Forward of the current chunk, in pieces: start (zero history, u^0 = 0) and
+// step n (with its checkpoint copy when due).  State u^n lives in the state
+// store when every state is kept, else in the ping-pong pair.
+void* fwd_state(const Ctx& c, bool store_all, int n) {
+  return store_all ? at(c.ws.states, n, c.S) : c.ws.work_u[n & 1];
+}
+
+int forward_start(Ctx& c, bool save) {
+  const bool store_all = save && c.p.ckpt_every == 0;
+  for (int k = 0; k < 3; ++k) RTE_CHECK(launch_zero(c.ws.lring[k], c.S, c.st));
+  RTE_CHECK(launch_zero(fwd_state(c, store_all, 0), c.S, c.st));
+  return RTE_OK;
+}
+
+int forward_op(Ctx& c, bool save, int n) {
+  const bool store_all = save && c.p.ckpt_every == 0;
+  const int64_t s = c.p.ckpt_every, S = c.S;
+  void* un = fwd_state(c, store_all, n);
+  if (save && s > 0 && n % s == 0) {
+    void* ck = at(c.ws.ckpts, (n / s) * 4, S);
+    RTE_CHECK(launch_copy(ck, un, S, c.st));
+    RTE_CHECK(launch_copy(at(ck, 1, S), c.ws.lring[(n + 2) % 3], S, c.st));
+    RTE_CHECK(launch_copy(at(ck, 2, S), c.ws.lring[(n + 1) % 3], S, c.st));
+    RTE_CHECK(launch_copy(at(ck, 3, S), c.ws.lring[n % 3], S, c.st));
+  }
+  return fwd_step(c, n, un, fwd_state(c, store_all, n + 1), c.ws.flux);
 }
 
 // Time loop of the forward for the current chunk (u^0 = 0, zero history);
 // writes the chunk's detector flux; keeps states or checkpoints when save.
 int forward_chunk(Ctx& c, bool save, void* u_final) {
-  Plan& p = c.p;
-  Workspace& ws = c.ws;
-  hipStream_t st = c.st;
-  const int64_t S = c.S;
-  for (int k = 0; k < 3; ++k) RTE_CHECK(launch_zero(ws.lring[k], S, st));
-  const bool store_all = save && p.ckpt_every == 0;
-  const int64_t s = p.ckpt_every;
-  void* u0 = store_all ? ws.states : ws.work_u[0];
-  RTE_CHECK(launch_zero(u0, S, st));
-  void* un = u0;
-  for (int n = 0; n < p.K; ++n) {
-    if (save && s > 0 && n % s == 0) {
-      void* ck = at(ws.ckpts, (n / s) * 4, S);
-      RTE_CHECK(launch_copy(ck, un, S, st));
-      RTE_CHECK(launch_copy(at(ck, 1, S), ws.lring[(n + 2) % 3], S, st));
-      RTE_CHECK(launch_copy(at(ck, 2, S), ws.lring[(n + 1) % 3], S, st));
-      RTE_CHECK(launch_copy(at(ck, 3, S), ws.lring[n % 3], S, st));
-    }
-    void* unp1 = store_all ? at(ws.states, n + 1, S) : ws.work_u[(n + 1) & 1];
-    int rc = fwd_step(c, n, un, unp1, ws.flux);
-    if (rc != RTE_OK) return rc;
-    un = unp1;
-  }
-  if (u_final) RTE_CHECK(launch_unpermute(p, un, u_final, st));
+  if (int rc = forward_start(c, save)) return rc;
+  for (int n = 0; n < c.p.K; ++n)
+    if (int rc = forward_op(c, save, n)) return rc;
+  if (u_final) RTE_CHECK(launch_unpermute(c.p, fwd_state(c, save && c.p.ckpt_every == 0, (int)c.p.K), u_final, c.st));
   return RTE_OK;
 }
+
+// Adjoint of the current chunk in pieces: start (zero ring and carries:
+// ubar^{K+1} = 0, v^{K+2..K+4} = 0), the restore of checkpoint j at the start
+// of segment j (checkpoint mode), and step n given u^n.
+int adjoint_start(Ctx& c) {
+  for (int k = 0; k < 4; ++k) RTE_CHECK(launch_zero(c.ws.vring[k], c.S, c.st));
+  RTE_CHECK(launch_zero(c.ws.atx, c.S, c.st));
+  RTE_CHECK(launch_zero(c.ws.aty, c.S, c.st));
+  RTE_CHECK(launch_zero(c.ws.ap1, c.S, c.st));
+  return RTE_OK;
+}
+
+int segment_restore(Ctx& c, int j) {
+  const int64_t S = c.S;
+  const int k0 = j * (int)c.p.ckpt_every;
+  void* ck = at(c.ws.ckpts, (int64_t)j * 4, S);
+  RTE_CHECK(launch_copy(c.ws.states, ck, S, c.st));
+  RTE_CHECK(launch_copy(c.ws.lring[(k0 + 2) % 3], at(ck, 1, S), S, c.st));
+  RTE_CHECK(launch_copy(c.ws.lring[(k0 + 1) % 3], at(ck, 2, S), S, c.st));
+  RTE_CHECK(launch_copy(c.ws.lring[k0 % 3], at(ck, 3, S), S, c.st));
+  return RTE_OK;
+}
+
+// Operation cursor: the gradient is a fixed sequence of operations and a
+// call enqueues those with index in [first, last).
+struct OpCursor {
+  int64_t first, last, idx;
+  bool take() {
+    const bool t = idx >= first && idx < last;
+    ++idx;
+    return t;
+  }
+};
 
 // Reverse time loop of the adjoint for the current chunk, whose forward
 // states (or checkpoints) are in the workspace and whose detector injection
 // is in ws.flux; accumulates the chunk's gradient partials into ga, gb.
-int adjoint_chunk(Ctx& c) {
+// Operations: start, then K adjoint steps (every state kept) or, per
+// segment from the last, the restore, the replay steps and the adjoint steps.
+int adjoint_ops(Ctx& c, OpCursor& r) {
   Plan& p = c.p;
-  Workspace& ws = c.ws;
-  hipStream_t st = c.st;
   const int64_t S = c.S;
   const int K = (int)p.K;
-  // zero adjoint ring and carries: ubar^{K+1} = 0, v^{K+2..K+4} = 0
-  for (int k = 0; k < 4; ++k) RTE_CHECK(launch_zero(ws.vring[k], S, st));
-  RTE_CHECK(launch_zero(ws.atx, S, st));
-  RTE_CHECK(launch_zero(ws.aty, S, st));
-  RTE_CHECK(launch_zero(ws.ap1, S, st));
+  if (r.take())
+    if (int rc = adjoint_start(c)) return rc;
   if (p.ckpt_every == 0) {
-    for (int n = K; n >= 1; --n) {
-      int rc = adj_step(c, n, at(ws.states, n, S));
-      if (rc != RTE_OK) return rc;
-    }
-  } else {
-    const int s = (int)p.ckpt_every;
-    const int nseg = (K + s - 1) / s;
-    for (int j = nseg - 1; j >= 0; --j) {
-      const int k0 = j * s, k1 = std::min(k0 + s, K);
-      void* ck = at(ws.ckpts, (int64_t)j * 4, S);
-      RTE_CHECK(launch_copy(ws.states, ck, S, st));
-      RTE_CHECK(launch_copy(ws.lring[(k0 + 2) % 3], at(ck, 1, S), S, st));
-      RTE_CHECK(launch_copy(ws.lring[(k0 + 1) % 3], at(ck, 2, S), S, st));
-      RTE_CHECK(launch_copy(ws.lring[k0 % 3], at(ck, 3, S), S, st));
-      for (int k = k0; k < k1; ++k) {
-        int rc = fwd_step(c, k, at(ws.states, k - k0, S), at(ws.states, k + 1 - k0, S), nullptr);
-        if (rc != RTE_OK) return rc;
-      }
-      for (int n = k1; n > k0; --n) {
-        int rc = adj_step(c, n, at(ws.states, n - k0, S));
-        if (rc != RTE_OK) return rc;
-      }
-    }
+    for (int n = K; n >= 1; --n)
+      if (r.take())
+        if (int rc = adj_step(c, n, at(c.ws.states, n, S))) return rc;
+    return RTE_OK;
+  }
+  const int s = (int)p.ckpt_every;
+  const int nseg = (K + s - 1) / s;
+  for (int j = nseg - 1; j >= 0; --j) {
+    const int k0 = j * s, k1 = std::min(k0 + s, K);
+    if (r.take())
+      if (int rc = segment_restore(c, j)) return rc;
+    for (int k = k0; k < k1; ++k)
+      if (r.take())
+        if (int rc = fwd_step(c, k, at(c.ws.states, k - k0, S), at(c.ws.states, k + 1 - k0, S), nullptr)) return rc;
+    for (int n = k1; n > k0; --n)
+      if (r.take())
+        if (int rc = adj_step(c, n, at(c.ws.states, n - k0, S))) return rc;
   }
   return RTE_OK;
+}
+
+int adjoint_chunk(Ctx& c) {
+  OpCursor r{0, INT64_MAX, 0};
+  return adjoint_ops(c, r);
 }
 
 int run_forward(Plan& p, const void* mu_a, const void* mu_s, double* G, void* u_final, int save, void* wsp,
                 int64_t wsb, hipStream_t st) {
   Workspace ws;
-  if (!map_or_fail(p, wsp, wsb, save != 0, &ws)) return RTE_ENOMEM;
+  if (int rc = map_or_fail(p, wsp, wsb, save != 0, &ws)) return rc;
   const int64_t S = state_stride_bytes(p);
   Ctx c{p, ws, st, mu_a, mu_s, S};
   p.have_forward = false;
@@ -231,9 +284,7 @@ int run_forward(Plan& p, const void* mu_a, const void* mu_s, double* G, void* u_
     }
   }
   reset_chunk(p);
-  p.have_forward = save != 0;
-  p.saved_chunk = save ? nc - 1 : -1;
-  p.saved_K = p.K;
+  if (save) mark_saved(p, wsp);
   return RTE_OK;
 }
 
@@ -245,8 +296,12 @@ int run_adjoint(Plan& p, const void* mu_a, const void* mu_s, const double* Gbar,
     set_error("rte_adjoint needs a preceding rte_forward with save_states=1 on this plan");
     return RTE_ESTATE;
   }
+  if (wsp != p.saved_ws) {
+    set_error("rte_adjoint needs the workspace of the saving forward (another buffer was passed)");
+    return RTE_ESTATE;
+  }
   Workspace ws;
-  if (!map_or_fail(p, wsp, wsb, true, &ws)) return RTE_ENOMEM;
+  if (int rc = map_or_fail(p, wsp, wsb, true, &ws)) return rc;
   const int64_t S = state_stride_bytes(p);
   Ctx c{p, ws, st, mu_a, mu_s, S};
   const int64_t gbytes = p.Nq * p.nx * p.ny * 8;
@@ -419,7 +474,7 @@ int forward_ex_chunk(Ctx& c, void* u_final) {
 int run_forward_ex(Plan& p, const void* mu_a, const void* mu_s, const rte_forward_extra* ex, double* G,
                    void* u_final, void* wsp, int64_t wsb, hipStream_t st) {
   Workspace ws;
-  if (!map_or_fail(p, wsp, wsb, false, &ws)) return RTE_ENOMEM;
+  if (int rc = map_or_fail(p, wsp, wsb, false, &ws)) return rc;
   const int64_t S = state_stride_bytes(p);
   Ctx c{p, ws, st, mu_a, mu_s, S};
   c.ext = ex;
@@ -456,43 +511,71 @@ std::vector<Out> grad_outputs(const Plan& p, const GradArgs& a) {
   return {{a.J, 1}, {a.dmu_a, p.nx * p.ny}, {a.dmu_s, p.nx * p.ny}, {a.G, p.Nq * p.Nd * p.K}};
 }
 
-// Forward with kept states, misfit and cotangent, adjoint, chunk by chunk:
-// all enqueued on st.
-int enqueue_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
+// The gradient as a fixed sequence of operations, chunk by chunk: op 0 zeroes
+// the detector flux and the gradient partials; per chunk, the forward start,
+// K forward steps (states or checkpoints kept), the misfit (detector
+// traces, J, cotangent, injection), then the adjoint operations of
+// adjoint_ops; the last op reduces the partials over the sources.  A call
+// enqueues the ops with index in [first, last) on st and returns the total
+// count in *n_ops; every op is a function of the plan, the arguments and
+// its index only, so consecutive ranges compose to the whole gradient bit
+// for bit.
+int enqueue_gradient_ops(Plan& p, const GradArgs& a, hipStream_t st, int64_t first, int64_t last, int64_t* n_ops) {
   Workspace ws;
-  if (!map_or_fail(p, a.ws, a.wsb, true, &ws)) return RTE_ENOMEM;
+  if (int rc = map_or_fail(p, a.ws, a.wsb, true, &ws)) return rc;
   const int64_t S = state_stride_bytes(p);
   Ctx c{p, ws, st, a.mu_a, a.mu_s, S};
-  p.have_forward = false;
-  RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
-  const int64_t gbytes = p.Nq * p.nx * p.ny * 8;
-  RTE_CHECK(launch_zero(ws.ga, gbytes, st));
-  RTE_CHECK(launch_zero(ws.gb, gbytes, st));
+  OpCursor r{first, last, 0};
   const int64_t nc = n_chunks(p);
   const int K = (int)p.K;
-  for (int64_t k = 0; k < nc; ++k) {
-    set_chunk(p, k);
-    int rc = forward_chunk(c, true, nullptr);
-    hipError_t e = hipSuccess;
-    if (rc == RTE_OK) e = launch_detect(p, ws.flux, a.G, K, st);
-    if (rc == RTE_OK && e == hipSuccess) e = launch_misfit(p, a.G, a.G_meas, ws.gbar, a.J, K, st);
-    if (rc == RTE_OK && e == hipSuccess) e = launch_inject(p, ws.gbar, ws.flux, K, st);
-    if (rc == RTE_OK && e != hipSuccess) {
-      set_error(std::string("detector/misfit kernel launch failed: ") + hipGetErrorString(e));
-      rc = RTE_EDEVICE;
+  auto body = [&]() -> int {
+    if (r.take()) {
+      p.have_forward = false;
+      RTE_CHECK(launch_zero(ws.flux, p.Nq * (p.K + 1) * 4 * p.npos * 8, st));
+      const int64_t gbytes = p.Nq * p.nx * p.ny * 8;
+      RTE_CHECK(launch_zero(ws.ga, gbytes, st));
+      RTE_CHECK(launch_zero(ws.gb, gbytes, st));
     }
-    if (rc == RTE_OK) rc = adjoint_chunk(c);
-    if (rc != RTE_OK) {
-      reset_chunk(p);
-      return rc;
+    for (int64_t k = 0; k < nc; ++k) {
+      set_chunk(p, k);
+      if (r.take())
+        if (int rc = forward_start(c, true)) return rc;
+      for (int n = 0; n < K; ++n)
+        if (r.take())
+          if (int rc = forward_op(c, true, n)) return rc;
+      if (r.take()) {
+        hipError_t e = launch_detect(p, ws.flux, a.G, K, st);
+        if (e == hipSuccess) e = launch_misfit(p, a.G, a.G_meas, ws.gbar, a.J, K, st);
+        if (e == hipSuccess) e = launch_inject(p, ws.gbar, ws.flux, K, st);
+        if (e != hipSuccess) {
+          set_error(std::string("detector/misfit kernel launch failed: ") + hipGetErrorString(e));
+          return RTE_EDEVICE;
+        }
+      }
+      if (int rc = adjoint_ops(c, r)) return rc;
     }
-  }
+    reset_chunk(p);
+    if (r.take()) {
+      RTE_CHECK(launch_grad_reduce(p, ws.ga, ws.gb, a.dmu_a, a.dmu_s, st));
+      mark_saved(p, a.ws);
+    }
+    return RTE_OK;
+  };
+  const int rc = body();
   reset_chunk(p);
-  RTE_CHECK(launch_grad_reduce(p, ws.ga, ws.gb, a.dmu_a, a.dmu_s, st));
-  p.have_forward = true;
-  p.saved_chunk = nc - 1;
-  p.saved_K = p.K;
-  return RTE_OK;
+  if (n_ops) *n_ops = r.idx;
+  return rc;
+}
+
+// Number of operations of one gradient (see enqueue_gradient_ops).
+int64_t gradient_op_count(const Plan& p) {
+  const int64_t K = p.K, s = p.ckpt_every;
+  const int64_t adj = s > 0 ? 1 + ((K + s - 1) / s) + 2 * K : 1 + K;
+  return 2 + n_chunks(p) * (1 + K + 1 + adj);
+}
+
+int enqueue_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
+  return enqueue_gradient_ops(p, a, st, 0, gradient_op_count(p), nullptr);
 }
 
 // Graph mode: record the whole sequence once per argument set, then replay.
@@ -500,7 +583,7 @@ int enqueue_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
 // gradient terms, chunk by chunk: all enqueued on st.
 int enqueue_gradient_continuous(Plan& p, const GradArgs& a, hipStream_t st) {
   Workspace ws;
-  if (!map_or_fail(p, a.ws, a.wsb, true, &ws)) return RTE_ENOMEM;
+  if (int rc = map_or_fail(p, a.ws, a.wsb, true, &ws)) return rc;
   const int64_t S = state_stride_bytes(p);
   Ctx c{p, ws, st, a.mu_a, a.mu_s, S};
   p.have_forward = false;
@@ -529,9 +612,7 @@ int enqueue_gradient_continuous(Plan& p, const GradArgs& a, hipStream_t st) {
   }
   reset_chunk(p);
   RTE_CHECK(launch_grad_reduce(p, ws.ga, ws.gb, a.dmu_a, a.dmu_s, st));
-  p.have_forward = true;
-  p.saved_chunk = nc - 1;
-  p.saved_K = p.K;
+  mark_saved(p, a.ws);
   return RTE_OK;
 }
 
@@ -565,7 +646,7 @@ int graph_gradient(Plan& p, const GradArgs& a, hipStream_t st) {
     p.gkey_sched = p.sched_version;
   }
   RTE_CHECK(hipGraphLaunch(p.gexec, st));
-  p.have_forward = true;
+  mark_saved(p, a.ws);
   return RTE_OK;
 }
 
@@ -605,12 +686,7 @@ struct TuneSet {
 int tune_setup(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t wsb, hipStream_t st, int nstates,
                TuneSet* t) {
   Workspace& ws = t->ws;
-  if (!map_workspace(p, wsp, wsb, true, &ws)) {
-    std::ostringstream o;
-    o << "workspace too small: need " << workspace_bytes(p, true) << " bytes";
-    set_error(o.str());
-    return RTE_ENOMEM;
-  }
+  if (int rc = map_or_fail(p, wsp, wsb, true, &ws)) return rc;
   p.have_forward = false;
   const int64_t S = state_stride_bytes(p);
   const int64_t cap = p.ckpt_every > 0 ? p.ckpt_every + 1 : p.K + 1;
@@ -785,6 +861,27 @@ bool nonnull(const void* p, const char* what) {
 
 }  // namespace
 
+namespace rte {
+
+// rte_forward without kept states into a caller-chosen device buffer; leaves
+// a forward saved in another workspace valid and records no profiling
+// events.
+int forward_into(Plan& p, const void* mu_a, const void* mu_s, double* G, void* u_final, void* buf, int64_t bytes,
+                 hipStream_t st) {
+  const bool had = p.have_forward, prof = p.prof;
+  const int64_t chunk = p.saved_chunk;
+  const void* sws = p.saved_ws;
+  p.prof = false;
+  const int rc = run_forward(p, mu_a, mu_s, G, u_final, 0, buf, bytes, st);
+  p.prof = prof;
+  p.have_forward = had;
+  p.saved_chunk = chunk;
+  p.saved_ws = sws;
+  return rc != RTE_OK ? rc : guard_check(p, st, {{G, p.Nq * p.Nd * p.K}});
+}
+
+}  // namespace rte
+
 extern "C" {
 
 int rte_plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams, const rte_detector* dets,
@@ -862,6 +959,58 @@ int rte_gradient(rte_plan* h, const void* mu_a, const void* mu_s, const double* 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int rc = p.use_graph ? graph_gradient(p, a, st) : enqueue_gradient(p, a, st);
     return rc != RTE_OK ? rc : guard_check(p, st, grad_outputs(p, a));
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return RTE_EINVAL;
+  }
+}
+
+int rte_gradient_ops(const rte_plan* h, int64_t* n_ops) {
+  if (!nonnull(h, "plan") || !nonnull(n_ops, "n_ops")) return RTE_EINVAL;
+  *n_ops = gradient_op_count(*reinterpret_cast<const Plan*>(h));
+  return RTE_OK;
+}
+
+int rte_gradient_range(rte_plan* h, const void* mu_a, const void* mu_s, const double* G_meas, double* J,
+                       double* dmu_a, double* dmu_s, double* G, void* workspace, int64_t workspace_bytes,
+                       int64_t first, int64_t last, void* stream) {
+  if (!nonnull(h, "plan") || !nonnull(mu_a, "mu_a") || !nonnull(mu_s, "mu_s") || !nonnull(G_meas, "G_meas") ||
+      !nonnull(J, "J") || !nonnull(dmu_a, "dmu_a") || !nonnull(dmu_s, "dmu_s") || !nonnull(G, "G") ||
+      !nonnull(workspace, "workspace"))
+    return RTE_EINVAL;
+  try {
+    set_error("");
+    Plan& p = *reinterpret_cast<Plan*>(h);
+    const int64_t total = gradient_op_count(p);
+    if (first < 0 || last < first || last > total) {
+      std::ostringstream o;
+      o << "op range [" << first << ", " << last << ") outside [0, " << total << "]";
+      set_error(o.str());
+      return RTE_EINVAL;
+    }
+    const void* key[9] = {mu_a, mu_s, G_meas, J, dmu_a, dmu_s, G, workspace,
+                          reinterpret_cast<const void*>(workspace_bytes)};
+    if (first == 0) {
+      for (int k = 0; k < 9; ++k) p.range_key[k] = key[k];
+      p.range_next = 0;
+    } else {
+      if (first != p.range_next) {
+        set_error("op ranges of one gradient must be enqueued in order, starting at 0");
+        return RTE_ESTATE;
+      }
+      for (int k = 0; k < 9; ++k)
+        if (p.range_key[k] != key[k]) {
+          set_error("op ranges of one gradient must pass the same arguments");
+          return RTE_ESTATE;
+        }
+    }
+    GradArgs a{mu_a, mu_s, G_meas, J, dmu_a, dmu_s, G, workspace, workspace_bytes};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    p.range_next = -1;
+    int rc = enqueue_gradient_ops(p, a, st, first, last, nullptr);
+    if (rc != RTE_OK) return rc;
+    p.range_next = last < total ? last : -1;
+    return last == total ? guard_check(p, st, grad_outputs(p, a)) : RTE_OK;
   } catch (const std::exception& e) {
     set_error(e.what());
     return RTE_EINVAL;
@@ -1102,6 +1251,7 @@ int rte_batch_gradient(rte_batch* h, const void* const* mu_a, const void* const*
       b.key = key;
     }
     RTE_CHECK(hipGraphLaunch(b.gexec, st));
+    for (size_t i = 0; i < n; ++i) mark_saved(*b.plans[i], args[i].ws);
     for (size_t i = 0; i < n; ++i)
       if (int rc = guard_check(*b.plans[i], st, grad_outputs(*b.plans[i], args[i]))) return rc;
     return RTE_OK;

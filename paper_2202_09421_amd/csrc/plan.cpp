@@ -16,6 +16,7 @@
 #include <cstring>
 #include <sstream>
 
+#include "fc_table_d5_C25.h"
 #include "rte_internal.h"
 
 namespace rte {
@@ -199,7 +200,7 @@ static bool validate(const rte_problem* p, const rte_beam* beams, int64_t nbm, c
   else if (!(p->dt > 0) || !(p->c > 0)) e << "dt and c must be positive";
   else if (!(std::fabs(p->g) < 1.0)) e << "|g| must be < 1";
   else if (!(p->n_in > 0) || !(p->n_out > 0)) e << "refractive indices must be positive";
-  else if (!p->fc_Q || !p->fc_A) e << "fc_Q and fc_A tables are required";
+  else if (!p->fc_Q != !p->fc_A) e << "fc_Q and fc_A must be given together (or both NULL)";
   else if (p->ckpt_every < 0) e << "ckpt_every must be >= 0";
   else if (p->combo_chunk < 0) e << "combo_chunk must be >= 0";
   else if (nbm < 0 || (nbm > 0 && !beams)) e << "bad beam array";
@@ -242,6 +243,9 @@ static bool validate(const rte_problem* p, const rte_beam* beams, int64_t nbm, c
           !(beams[k].sigma_t > 0)) {
         e << "beam " << k << " has a bad group or width";
         break;
+      } else if (beams[k].profile != RTE_PROFILE_GAUSSIAN && beams[k].profile != RTE_PROFILE_WINDOW) {
+        e << "beam " << k << " has an unknown temporal profile " << beams[k].profile;
+        break;
       }
     for (int64_t k = 0; k < nd; ++k)
       if (!(dets[k].sigma_d > 0)) {
@@ -272,6 +276,19 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
   }
   *out = nullptr;
   if (!validate(prob, beams, n_beams, dets, n_det)) return RTE_EINVAL;
+  // FC table: the caller's, or the built-in one for (d, C) = (5, 25)
+  rte_problem pbt = *prob;
+  if (!prob->fc_Q) {
+    if (prob->fc_d != kBuiltinFcD || prob->fc_C != kBuiltinFcC) {
+      std::ostringstream o;
+      o << "no built-in FC table for fc_d = " << prob->fc_d << ", fc_C = " << prob->fc_C
+        << " (built in: " << kBuiltinFcD << ", " << kBuiltinFcC << "): pass fc_Q and fc_A";
+      set_error(o.str());
+      return RTE_EUNSUPPORTED;
+    }
+    pbt.fc_Q = kBuiltinFcQ;
+    pbt.fc_A = kBuiltinFcA;
+  }
   Plan* P = new Plan();
   Plan& p = *P;
   p.prob = *prob;
@@ -478,16 +495,20 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
       dd = std::min(dd, 2.0 * kPi - dd);
       ban[(size_t)kk * M + s] = window_fn(dd / b.sigma_theta);
     }
+    // temporal profile T(t - tau) of eq. (RTEsources2): Gaussian, or the
+    // window of eq. (sourcelabwind) in |t - t_s| / sigma_t as in eq. (sourcelab)
     for (int64_t n = 0; n <= p.K; ++n) {
-      const double t = n * prob->dt;
-      btt[(size_t)kk * (p.K + 1) + n] = std::exp(-((t - b.tau - b.t0) * (t - b.tau - b.t0)) / (2.0 * b.sigma_t * b.sigma_t));
+      const double dtt = n * prob->dt - b.tau - b.t0;
+      btt[(size_t)kk * (p.K + 1) + n] = b.profile == RTE_PROFILE_WINDOW
+                                            ? window_fn(dtt / b.sigma_t)
+                                            : std::exp(-(dtt * dtt) / (2.0 * b.sigma_t * b.sigma_t));
     }
   }
 
   // ---- FC plans
   std::vector<double> fcbuf;
   std::vector<size_t> ox, oy;
-  if (!build_fc(*prob, (int)p.nx, dx, fcbuf, p.fcx, ox) || !build_fc(*prob, (int)p.ny, dy, fcbuf, p.fcy, oy)) {
+  if (!build_fc(pbt, (int)p.nx, dx, fcbuf, p.fcx, ox) || !build_fc(pbt, (int)p.ny, dy, fcbuf, p.fcy, oy)) {
     set_error("FC extended length needs too many FFT passes");
     delete P;
     return RTE_EUNSUPPORTED;

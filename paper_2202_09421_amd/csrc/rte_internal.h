@@ -110,6 +110,11 @@ struct Plan {
   int64_t saved_chunk = -1;    // chunk whose forward states are in the workspace
   bool have_forward = false;   // a saved forward lives in the workspace
   int64_t saved_K = 0;
+  const void* saved_ws = nullptr;  // workspace base of the saved forward
+  // staged gradient (rte_gradient_range): next op expected and the
+  // argument pointers of the sequence in progress
+  int64_t range_next = -1;
+  const void* range_key[9] = {nullptr};
   // graph mode: rte_gradient recorded once per argument set, then replayed
   bool use_graph = false;
   bool guard = false;          // scan outputs for NaN / Inf after each call
@@ -151,6 +156,11 @@ struct Workspace {
   double* gbar = nullptr;    // [Nq][Nd][K] misfit cotangent (rte_gradient)
   double* scratch = nullptr; // small reductions
 };
+
+// rte_forward without kept states into the device buffer [buf, buf + bytes)
+// (256-byte aligned); a forward saved in another workspace stays valid
+int forward_into(Plan& p, const void* mu_a, const void* mu_s, double* G, void* u_final, void* buf, int64_t bytes,
+                 hipStream_t st);
 
 int64_t state_elems(const Plan& p);
 // bytes between consecutive state arrays of the workspace

@@ -21,8 +21,6 @@ import os
 import numpy as np
 import torch
 
-from .fc_tables import fc_tables
-
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librte.so")
 
@@ -50,7 +48,10 @@ class rte_problem(ctypes.Structure):
 
 class rte_beam(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("x", "y", "theta", "sigma_x", "sigma_theta", "tau", "sigma_t", "t0")] + \
-               [("group", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+               [("group", ctypes.c_int32), ("profile", ctypes.c_int32)]
+
+
+RTE_PROFILE = {"gauss": 0, "window": 1}
 
 
 class rte_detector(ctypes.Structure):
@@ -99,6 +100,8 @@ def lib():
         L.rte_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp]
         L.rte_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
         L.rte_gradient_continuous.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.rte_gradient_ops.argtypes = [vp, ctypes.POINTER(i64)]
+        L.rte_gradient_range.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, i64, vp]
         L.rte_forward_ex.argtypes = [vp, vp, vp, ctypes.POINTER(rte_forward_extra), vp, vp, vp, i64, vp]
         L.rte_plan_set_graph.argtypes = [vp, ctypes.c_int]
         L.rte_plan_set_guard.argtypes = [vp, ctypes.c_int]
@@ -118,7 +121,7 @@ def lib():
                   "rte_adjoint", "rte_gradient", "rte_profile_enable", "rte_profile_read", "rte_plan_set_graph",
                   "rte_batch_create", "rte_batch_destroy", "rte_batch_gradient", "rte_plan_get_schedule",
                   "rte_plan_set_schedule", "rte_plan_autotune", "rte_plan_time_kernels", "rte_gradient_continuous",
-                  "rte_forward_ex", "rte_plan_set_guard"):
+                  "rte_forward_ex", "rte_plan_set_guard", "rte_gradient_ops", "rte_gradient_range"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -137,11 +140,10 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def make_problem(spec, dtype=RTE_F64, ckpt_every=0, combo_chunk=0):
-    """Build the C structs for a problem description (see module docstring)."""
-    Q, A = fc_tables(spec.fc_d, spec.fc_C)
-    Qc = np.ascontiguousarray(Q, dtype=np.float64)
-    Ac = np.ascontiguousarray(A, dtype=np.float64)
+def make_problem(spec, dtype=RTE_F64, ckpt_every=0, combo_chunk=0, fc_QA=None):
+    """Build the C structs for a problem description (see module docstring).
+    fc_QA: optional (Q [d, d], A [C, d]) FC table; None uses the library's
+    built-in table (d = 5, C = 25)."""
     p = rte_problem()
     p.dtype = dtype
     p.Nx, p.Ny, p.M, p.K = spec.Nx, spec.Ny, spec.M, spec.K
@@ -150,28 +152,34 @@ def make_problem(spec, dtype=RTE_F64, ckpt_every=0, combo_chunk=0):
     p.n_in, p.n_out = spec.n_in, spec.n_out
     p.fc_d, p.fc_C = spec.fc_d, spec.fc_C
     p.filt_alpha, p.filt_beta = spec.filt_alpha, spec.filt_beta
-    p.fc_Q = Qc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    p.fc_A = Ac.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    keep = ()
+    if fc_QA is not None:
+        Qc = np.ascontiguousarray(fc_QA[0], dtype=np.float64)
+        Ac = np.ascontiguousarray(fc_QA[1], dtype=np.float64)
+        p.fc_Q = Qc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.fc_A = Ac.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        keep = (Qc, Ac)
     p.ckpt_every = ckpt_every
     p.combo_chunk = combo_chunk
     beams = (rte_beam * max(1, len(spec.beams)))()
     for k, b in enumerate(spec.beams):
-        beams[k] = rte_beam(b.x, b.y, b.theta, b.sigma_x, b.sigma_theta, b.tau, b.sigma_t, b.t0, b.group, 0)
+        beams[k] = rte_beam(b.x, b.y, b.theta, b.sigma_x, b.sigma_theta, b.tau, b.sigma_t, b.t0, b.group,
+                            RTE_PROFILE[getattr(b, "profile", "gauss")])
     dets = (rte_detector * max(1, len(spec.detectors)))()
     for k, dd in enumerate(spec.detectors):
         dets[k] = rte_detector(dd.x, dd.y, dd.sigma_d)
-    return p, beams, len(spec.beams), dets, len(spec.detectors), (Qc, Ac)
+    return p, beams, len(spec.beams), dets, len(spec.detectors), keep
 
 
 class Plan:
     """A library plan for one problem description (all Nq sources)."""
 
-    def __init__(self, spec, dtype=torch.float64, ckpt_every=0, device=None, combo_chunk=0):
+    def __init__(self, spec, dtype=torch.float64, ckpt_every=0, device=None, combo_chunk=0, fc_QA=None):
         self.spec = spec
         self.dtype = dtype
         self.device = torch.device("cuda") if device is None else torch.device(device)
         code = RTE_F64 if dtype == torch.float64 else RTE_F32
-        prob, beams, nb, dets, nd, self._keep = make_problem(spec, code, ckpt_every, combo_chunk)
+        prob, beams, nb, dets, nd, self._keep = make_problem(spec, code, ckpt_every, combo_chunk, fc_QA)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().rte_plan_create(ctypes.byref(prob), beams, nb, dets, nd, ctypes.byref(h)))
@@ -182,6 +190,9 @@ class Plan:
         self._ws = None
         self._graph = False
         self._gout = None
+        # bumped by every call that rewrites the workspace; RTEFunction
+        # checks it to know whether its saved forward is still there
+        self.generation = 0
 
     def close(self):
         """Destroy the library plan and drop the workspace and output buffers
@@ -226,6 +237,7 @@ class Plan:
             uK = torch.empty((self.Nq, self.spec.Ny + 1, self.spec.Nx + 1, self.spec.M), dtype=self.dtype,
                              device=self.device)
         ws = self.workspace(save_states)
+        self.generation += 1
         _check(lib().rte_forward(self._h, _ptr(a), _ptr(b), _ptr(G), _ptr(uK), 1 if save_states else 0,
                                  _ptr(ws), ws.numel(), _stream()))
         self._medium_saved = (a, b)
@@ -287,6 +299,7 @@ class Plan:
         a, b = self._medium(mu_a, mu_s)
         ws = self.workspace(True)
         sc = rte_schedule()
+        self.generation += 1
         _check(lib().rte_plan_autotune(self._h, _ptr(a), _ptr(b), _ptr(ws), ws.numel(), _stream(), ctypes.byref(sc)))
         chosen = sc.as_dict()
         if path:
@@ -308,6 +321,7 @@ class Plan:
         a, b = self._medium(mu_a, mu_s)
         ws = self.workspace(True)
         us = (ctypes.c_double * len(KERNEL_CLASSES))()
+        self.generation += 1
         _check(lib().rte_plan_time_kernels(self._h, _ptr(a), _ptr(b), _ptr(ws), ws.numel(), _stream(), int(reps), us))
         return {k: us[i] for i, k in enumerate(KERNEL_CLASSES)}
 
@@ -339,8 +353,36 @@ class Plan:
         gm = torch.as_tensor(G_meas, dtype=torch.float64, device=self.device).contiguous()
         J, da, db, G = self._outputs()
         ws = self.workspace(True)
+        self.generation += 1
         _check(lib().rte_gradient(self._h, _ptr(a), _ptr(b), _ptr(gm), _ptr(J), _ptr(da), _ptr(db), _ptr(G),
                                   _ptr(ws), ws.numel(), _stream()))
+        return J, da, db, G
+
+    def gradient_ops(self):
+        """Number of operations of one gradient (rte_gradient_ops)."""
+        n = ctypes.c_int64()
+        _check(lib().rte_gradient_ops(self._h, ctypes.byref(n)))
+        return n.value
+
+    def gradient_range(self, mu_a, mu_s, G_meas, first, last):
+        """Enqueue operations [first, last) of one gradient (rte_gradient_range).
+        Ranges of one gradient go in order from 0 with the same tensors; the
+        outputs (J, dmu_a, dmu_s, G), owned by the plan and reused by every
+        staged gradient, are complete after the range holding the last op."""
+        a, b = self._medium(mu_a, mu_s)
+        gm = torch.as_tensor(G_meas, dtype=torch.float64, device=self.device).contiguous()
+        if first == 0 or getattr(self, "_rng", None) is None:
+            ny, nx = self.spec.Ny + 1, self.spec.Nx + 1
+            mk = lambda *sh: torch.empty(sh, dtype=torch.float64, device=self.device)
+            if getattr(self, "_rng_out", None) is None:
+                self._rng_out = (mk(1), mk(ny, nx), mk(ny, nx), mk(self.Nq, self.Nd, self.spec.K))
+            self._rng = (a, b, gm)   # the inputs stay alive (and equal) for the whole sequence
+        a, b, gm = self._rng
+        J, da, db, G = self._rng_out
+        ws = self.workspace(True)
+        self.generation += 1
+        _check(lib().rte_gradient_range(self._h, _ptr(a), _ptr(b), _ptr(gm), _ptr(J), _ptr(da), _ptr(db), _ptr(G),
+                                        _ptr(ws), ws.numel(), int(first), int(last), _stream()))
         return J, da, db, G
 
 
@@ -402,6 +444,7 @@ class Plan:
             uK = torch.empty((self.Nq, self.spec.Ny + 1, self.spec.Nx + 1, self.spec.M), dtype=self.dtype,
                              device=self.device)
         ws = self.workspace(False)
+        self.generation += 1
         _check(lib().rte_forward_ex(self._h, _ptr(a), _ptr(b), ctypes.byref(ex), _ptr(G), _ptr(uK), _ptr(ws),
                                     ws.numel(), _stream()))
         # the tables in `keep` may be released now: later allocations reuse
@@ -418,6 +461,7 @@ class Plan:
         mk = lambda *sh: torch.empty(sh, dtype=torch.float64, device=self.device)
         J, da, db, G = mk(1), mk(ny, nx), mk(ny, nx), mk(self.Nq, self.Nd, self.spec.K)
         ws = self.workspace(True)
+        self.generation += 1
         _check(lib().rte_gradient_continuous(self._h, _ptr(a), _ptr(b), _ptr(gm), _ptr(J), _ptr(da), _ptr(db),
                                              _ptr(G), _ptr(ws), ws.numel(), _stream()))
         return J, da, db, G
@@ -467,6 +511,8 @@ class Batch:
         db = [o[2] for o in self._out]
         G = [o[3] for o in self._out]
         wb = (ctypes.c_int64 * n)(*[w.numel() for w in wss])
+        for p in self.plans:
+            p.generation += 1
         _check(lib().rte_batch_gradient(self._h, arr([x[0] for x in ins]), arr([x[1] for x in ins]), arr(gms),
                                         arr(J), arr(da), arr(db), arr(G), arr(wss), wb, _stream()))
         return J, da, db, G
@@ -491,18 +537,27 @@ def profile_read(plan):
 class RTEFunction(torch.autograd.Function):
     """G = F(mu_a, mu_s): detector traces [Nq, Nd, K] of the forward solve.
     backward runs the library's exact discrete adjoint (checkpointed replay
-    when the plan was made with ckpt_every > 0)."""
+    when the plan was made with ckpt_every > 0).  If another call rewrote the
+    plan's workspace after this forward (a second application of the
+    Function, a gradient, a line-search trial), backward first re-runs the
+    forward with the saved medium so that the adjoint pairs with its own
+    states."""
 
     @staticmethod
     def forward(ctx, mu_a, mu_s, plan):
         ctx.plan = plan
         ctx.save_for_backward(mu_a, mu_s)
-        return plan.forward(mu_a.detach(), mu_s.detach(), save_states=True)
+        G = plan.forward(mu_a.detach(), mu_s.detach(), save_states=True)
+        ctx.generation = plan.generation
+        return G
 
     @staticmethod
     def backward(ctx, grad_G):
         mu_a, mu_s = ctx.saved_tensors
-        da, db = ctx.plan.adjoint(grad_G.contiguous(), mu_a.detach(), mu_s.detach())
+        plan = ctx.plan
+        if plan.generation != ctx.generation:
+            plan.forward(mu_a.detach(), mu_s.detach(), save_states=True)
+        da, db = plan.adjoint(grad_G.contiguous(), mu_a.detach(), mu_s.detach())
         return da.to(mu_a.dtype), db.to(mu_s.dtype), None
 
 

@@ -1,6 +1,7 @@
 """CPU checks of the C-ABI library: it loads, exports every declared entry
 point, and rejects bad problem descriptions before touching the device.
-Also the library's host-side FC table builder against the oracle's."""
+Also the library's FC table (built in, and its generator) against the
+oracle's."""
 import ctypes
 import os
 import re
@@ -121,3 +122,60 @@ def test_binding_struct_layouts_match_header(tmp_path):
         assert int(got[S.__name__]) == ctypes.sizeof(S), S.__name__
         for f in S._fields_:
             assert int(got["%s.%s" % (S.__name__, f[0])]) == getattr(S, f[0]).offset, (S.__name__, f[0])
+
+
+def test_builtin_fc_table_is_the_generated_one():
+    """csrc/fc_table_d5_C25.h holds exactly what the committed generator
+    writes from fc_tables(5, 25) (hexadecimal doubles, bit for bit)."""
+    from paper_2202_09421_amd import gen_fc_table
+    assert open(gen_fc_table.OUT).read() == gen_fc_table.render()
+    from paper_2202_09421_amd.fc_tables import fc_tables
+    Q, A = fc_tables(5, 25)
+    vals = [float.fromhex(v) for v in re.findall(r"(-?0x[0-9a-fp.+-]+),", open(gen_fc_table.OUT).read())]
+    assert np.array_equal(np.array(vals), np.concatenate([Q.reshape(-1), A.reshape(-1)]))
+
+
+def _create(prob, beams, nb, dets, nd):
+    L = _lib()
+    h = ctypes.c_void_p()
+    rc = L.rte_plan_create(ctypes.byref(prob), beams, nb, dets, nd, ctypes.byref(h))
+    if h.value:
+        L.rte_plan_destroy(h)
+    return rc, L.rte_last_error().decode()
+
+
+def test_plan_create_with_null_fc_tables_uses_the_builtin_one():
+    """A plain C caller passes no table: validation accepts it for (5, 25);
+    without a GPU the call then stops at the device upload."""
+    from paper_2202_09421_amd import rte
+    prob, beams, nb, dets, nd, keep = _bad_problem()
+    assert not prob.fc_Q and not prob.fc_A
+    rc, msg = _create(prob, beams, nb, dets, nd)
+    assert rc in (rte.RTE_OK, rte.RTE_EDEVICE), msg
+    if rc == rte.RTE_EDEVICE:
+        assert "upload" in msg
+    prob.fc_d = 4
+    rc, msg = _create(prob, beams, nb, dets, nd)
+    assert rc == rte.RTE_EUNSUPPORTED and "no built-in FC table" in msg
+
+
+def test_plan_create_rejects_half_a_table_and_unknown_profiles():
+    from paper_2202_09421_amd import rte
+    prob, beams, nb, dets, nd, keep = _bad_problem()
+    Q = (ctypes.c_double * 25)()
+    prob.fc_Q = ctypes.cast(Q, ctypes.POINTER(ctypes.c_double))
+    rc, msg = _create(prob, beams, nb, dets, nd)
+    assert rc == rte.RTE_EINVAL and "together" in msg
+    prob, beams, nb, dets, nd, keep = _bad_problem()
+    beams[0].profile = 7
+    rc, msg = _create(prob, beams, nb, dets, nd)
+    assert rc == rte.RTE_EINVAL and "temporal profile" in msg
+
+
+def test_staged_gradient_argument_checks():
+    from paper_2202_09421_amd import rte
+    L = _lib()
+    n = ctypes.c_int64()
+    assert L.rte_gradient_ops(None, ctypes.byref(n)) == rte.RTE_EINVAL
+    assert L.rte_gradient_range(None, None, None, None, None, None, None, None, None, 0, 0, 0, None) == rte.RTE_EINVAL
+    assert "NULL" in L.rte_last_error().decode()
