@@ -65,7 +65,7 @@ class Oracle:
         self.inflow = None  # optional callable t -> values on the BC entries
         if dense_derivative:
             for op in (self.Dx, self.Dy):
-                Dm = op.dense()
+                Dm = np.ascontiguousarray(op.dense())   # contiguous: the product runs in BLAS
                 op.derivative = (lambda D: lambda g, axis=-1: np.moveaxis(np.moveaxis(g, axis, -1) @ D.T, -1, axis))(Dm)
                 op.derivative_T = (lambda D: lambda y, axis=-1: np.moveaxis(np.moveaxis(y, axis, -1) @ D, -1, axis))(Dm)
 
