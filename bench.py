@@ -1,16 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the FC-DOM forward + adjoint gradient on one MI355X.
 
-One benchmark step = one full gradient evaluation of the FP64 gradient
-workload (4 x 4 cm, 257 x 257 nodes, 32 ordinates, HG g = 0.9, Fresnel
-n = 1.4, background mu_a = 0.2 / mu_s = 50 per cm, 1 beam, 32 detectors,
-2000 AB4 steps): forward solve with every state kept, misfit against
-synthetic measurements (forward solve on the medium with three inclusions,
-10 % multiplicative noise), exact discrete adjoint, dJ/dmu_a and dJ/dmu_s.
+Default workload (the metric's configuration): the batched multiple-
+staggered-source problem, 6 x 6 cm, 513 x 513 nodes, 64 ordinates, HG
+g = 0.9, Fresnel n = 1.4, background mu_a = 0.2 / mu_s = 50 per cm (three
+inclusions in the true medium), 16 beams fired as 8 combinations of two with
+seeded delays 0..100 ps, 64 detectors, 6000 AB4 steps, FP64.  One gradient
+evaluation: forward of all 8 combinations with checkpoints, misfit against
+synthetic measurements (forward on the medium with inclusions, 10 %
+multiplicative noise), checkpointed segment replay and exact discrete
+adjoint, dJ/dmu_a and dJ/dmu_s.  "batched": combination chunks as large as
+HBM allows (every launch covers a whole chunk); "plain": one combination per
+launch, one after another.
 
-value = cells * ordinates * time steps * sources / seconds per gradient
+One benchmark step = one slice of the batched gradient: the gradient's fixed
+sequence of operations (rte_gradient_ops) cut into --steps ranges of equal
+operation count (rte_gradient_range), so the --steps timed steps are exactly
+one whole gradient (bit-identical to one rte_gradient call) and
+steps x ms_per_step is its wall time.  Warmup steps run the first --warmup
+slices of another gradient.  The plain gradient is timed as one call.
+
+value = cells * ordinates * time steps * combinations / seconds per gradient
 (a unit is one node x one ordinate x one step, counted once for the whole
-forward + adjoint pair).  Inputs are resident in HBM before the timed region.
+forward + replay + adjoint).  Inputs are resident in HBM before the timed
+region.
 
 Prints one JSON line (last line of stdout).
 """
@@ -37,13 +50,20 @@ KERNEL_WORDS = {
     "lines_adj": 4,    # x and y lines: read w twice, write Dx^T(xi w) and Dy^T(eta w)
 }
 PATH_WORDS_STORE_ALL = 12  # algorithmic fwd + adj per unit: 6 + 6 words
+PATH_WORDS_REPLAY = 19     # with one-level checkpoint replay: 6 + 6 + 6 + 1 store
+# algorithmic words per unit of one launch: a node pass completes one time step
+# (forward: read u, L^{n-1..n-3}, write u, L^n; adjoint: read v^{n+1..n+4}, u^n,
+# write v^n); the line passes only move intermediates and are charged their
+# own compulsory words
+ALGO_WORDS = {"node_fwd": 6, "node_adj": 6, "lines_fwd": 4, "lines_adj": 4}
 
 # kernel class -> row label in the committed HBM counter summary
 TRAFFIC_ROWS = {
     "lines_fwd": "x and y line derivatives (fwd)", "node_fwd": "node pass (fwd)",
     "node_adj": "node pass (adj)", "lines_adj": "x and y line transposes (adj)",
 }
-TRAFFIC_FILE = {"f64": "profiles/gradient_fp64_257x257_M32_K2000_hbm_traffic.md"}
+TRAFFIC_FILE = {("gradient257", "f64"): "profiles/gradient_fp64_257x257_M32_K2000_hbm_traffic.md",
+                ("mss", "f64"): "profiles/mss_fp64_513x513_M64_chunk4_hbm_traffic.md"}
 
 
 def source_hash():
@@ -61,12 +81,12 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(dtype, cls):
+def measured_traffic(workload, dtype, cls):
     """HBM bytes per launch of kernel class `cls` from the committed
     FETCH_SIZE / WRITE_SIZE summary (already scaled by the copy calibration),
     or None when no summary exists or the kernels changed since it was taken."""
     import re
-    name = TRAFFIC_FILE.get(dtype)
+    name = TRAFFIC_FILE.get((workload, dtype))
     if name is None or not os.path.exists(os.path.join(ROOT, name)):
         return None
     with open(os.path.join(ROOT, name)) as fh:
@@ -496,11 +516,227 @@ def lab_flux_workload(log_fn):
     return out
 
 
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline_sample(spec, target_s, cores, what):
+    """Time the FP64 oracle (forward + exact adjoint gradient, all states
+    kept) on the first steps of `spec` with `cores` threads (BLAS and FFT);
+    returns the cpu_baseline record."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import fc as ofc
+    from oracle.solver import Oracle
+
+    ofc.set_fft_workers(None if cores == 1 else cores)
+    try:
+        with threadpool_limits(limits=cores):
+            o = Oracle(spec.with_(K=1))
+            t0 = time.perf_counter()
+            o.gradient(np.zeros((spec.Nq, len(spec.detectors), 1)))
+            per_step = time.perf_counter() - t0
+            Ks = int(max(2, min(60, target_s / max(per_step, 1e-3))))
+            o = Oracle(spec.with_(K=Ks))
+            t0 = time.perf_counter()
+            o.gradient(np.zeros((spec.Nq, len(spec.detectors), Ks)))
+            dt = time.perf_counter() - t0
+    finally:
+        ofc.set_fft_workers(None)
+    units = (spec.Nx + 1) * (spec.Ny + 1) * spec.M * Ks * spec.Nq
+    return {"value": units / dt, "unit": "cell*ordinate*steps/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d of %d steps of %s, forward + exact adjoint gradient with every state kept "
+                      "(no replay), NumPy/SciPy FP64, %d thread(s), %.1f s" % (Ks, spec.K, what, cores, dt)}
+
+
+def mss_headline(args, log_fn):
+    """The batched MSS gradient (513 x 513 nodes, 64 ordinates, 8 combinations,
+    6000 steps, checkpointed) sliced into --steps operation ranges, against the
+    plain (one combination per launch) gradient; per-kernel launch times, the
+    roofline of the dominant kernel class and of the whole path."""
+    import dataclasses
+    import math
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2202_09421_amd import rte
+
+    tdt = torch.float64 if args.dtype == "f64" else torch.float32
+    full = W.config(2)
+    spec = full.with_(K=args.workload_steps) if args.workload_steps else full
+    nx, ny = spec.Nx + 1, spec.Ny + 1
+    units = nx * ny * spec.M * spec.K * spec.Nq
+    ckpt = min(spec.K, max(8, int(round(math.sqrt(4 * spec.K)))))
+    a_true = torch.tensor(spec.mu_a, device="cuda", dtype=tdt)
+    b_true = torch.tensor(spec.mu_s, device="cuda", dtype=tdt)
+    a_bg = torch.full((ny, nx), 0.2, device="cuda", dtype=tdt)
+    b_bg = torch.full((ny, nx), 50.0, device="cuda", dtype=tdt)
+
+    # batched: the largest combination chunk that fits in 85 % of free HBM,
+    # chunk sizes as even as possible
+    free = torch.cuda.mem_get_info()[0]
+    chunk = spec.Nq
+    while chunk > 1 and not args.combo_chunk:
+        probe = rte.Plan(spec, tdt, ckpt_every=ckpt, combo_chunk=chunk)
+        need = probe.workspace_bytes(True)
+        probe.close()
+        if need <= 0.85 * free:
+            break
+        chunk -= 1
+    chunk = args.combo_chunk or -(-spec.Nq // -(-spec.Nq // chunk))
+    plan = rte.Plan(spec, tdt, ckpt_every=ckpt, combo_chunk=chunk)
+    ws_gb = plan.workspace_bytes(True) / 1e9
+    if args.schedule:
+        plan.set_schedule(json.loads(args.schedule))
+        sched = dict(plan.schedule(), cached=None)
+    else:
+        sched = plan.autotune(a_bg, b_bg, cache=args.tune_cache if args.tune_cache else False)
+    sched = {k: v for k, v in sched.items() if k != "cached"}
+    log_fn("bench: %s %s, %d combinations in chunks of %d, checkpoint every %d steps, workspace %.1f GB, "
+           "schedule %s" % (spec.name, args.dtype, spec.Nq, chunk, ckpt, ws_gb, sched))
+    G_true = plan.forward(a_true, b_true)
+    noise = torch.tensor(W.measured_noise(3, tuple(G_true.shape)), device="cuda")
+    Gm = (G_true * noise).contiguous()
+    del G_true
+    torch.cuda.synchronize()
+    log_fn("bench: measurements (forward on the medium with inclusions) done")
+
+    if args.profile_run:
+        plan.gradient(a_bg, b_bg, Gm)
+        torch.cuda.synchronize()
+        log_fn("bench: profile run done")
+        return None
+
+    n_ops = plan.gradient_ops()
+    S = args.steps
+    cuts = [(i * n_ops) // S for i in range(S + 1)]
+    for k in range(args.warmup):
+        plan.gradient_range(a_bg, b_bg, Gm, cuts[k % S], cuts[k % S + 1])
+        torch.cuda.synchronize()
+        log_fn("bench: warmup slice %d done" % k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(S):
+        out = plan.gradient_range(a_bg, b_bg, Gm, cuts[k], cuts[k + 1])
+        if k % max(1, S // 10) == 0:
+            log_fn("bench: slice %d of %d enqueued" % (k, S))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    Jb, gab, gbb = (x.clone() for x in out[:3])
+    log_fn("bench: batched gradient in %d slices: %.2f s (J = %.6e)" % (S, elapsed, float(Jb.item())))
+    if not np.isfinite(float(Jb.item())) or not torch.isfinite(gab).all():
+        raise RuntimeError("non-finite gradient")
+    reps = 20
+    kus = plan.time_kernels(a_bg, b_bg, reps=reps)
+    log_fn("bench: per-launch kernel times (us) %s" % {k: round(v, 1) for k, v in kus.items()})
+    plan.close()
+    del plan, out
+    torch.cuda.empty_cache()
+
+    plain = None
+    if not args.no_plain:
+        pp = rte.Plan(spec, tdt, ckpt_every=ckpt, combo_chunk=1)
+        psched = pp.autotune(a_bg, b_bg, cache=False) if not args.schedule else sched
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Jp, gap, gbp, _ = pp.gradient(a_bg, b_bg, Gm)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        rel = lambda x, y: float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y))
+        plain = {"value": units / tp, "seconds": tp, "combo_chunk": 1,
+                 "schedule": {k: v for k, v in psched.items() if k != "cached"},
+                 "gradients_bitwise_equal": bool(torch.equal(gap, gab) and torch.equal(gbp, gbb)),
+                 "J_rel_diff": abs(float(Jp.item()) - float(Jb.item())) / abs(float(Jb.item())),
+                 "gradient_max_rel_diff": max(rel(gap, gab), rel(gbp, gbb))}
+        log_fn("bench: plain gradient (one combination per launch): %.2f s" % tp)
+        pp.close()
+        del pp
+        torch.cuda.empty_cache()
+
+    # launches per gradient of each class: forward and replay steps, adjoint steps
+    nch = -(-spec.Nq // chunk)
+    per_grad = {"lines_fwd": 2 * spec.K * nch, "node_fwd": 2 * spec.K * nch,
+                "node_adj": spec.K * nch, "lines_adj": spec.K * nch}
+    upl = nx * ny * spec.M * chunk  # units per launch (a full chunk)
+    word = WORD[args.dtype]
+    kernels = {}
+    for cls, us in kus.items():
+        kernels[cls] = {"avg_us": round(us, 2), "launches_per_gradient": per_grad[cls],
+                        "ms_per_gradient": round(us * per_grad[cls] / 1000.0, 1),
+                        "algorithmic_GB_s": round(ALGO_WORDS[cls] * word * upl / (us * 1e-6) / 1e9, 1),
+                        "compulsory_GB_s": round(KERNEL_WORDS[cls] * word * upl / (us * 1e-6) / 1e9, 1)}
+    tot = sum(k["ms_per_gradient"] for k in kernels.values())
+    for k in kernels.values():
+        k["share"] = round(k["ms_per_gradient"] / tot, 3)
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_gradient"])
+    ach = kernels[dom]["algorithmic_GB_s"]
+    algo_bytes = ALGO_WORDS[dom] * word * upl
+    traffic = measured_traffic("mss", args.dtype, dom)
+    value = units / elapsed
+    path_gbs = value * PATH_WORDS_REPLAY * word / 1e9
+    out = {
+        "metric": "cell*ordinate*steps/s fwd+adjoint on 1 GPU, batched vs plain, at rel-L2 1e-10",
+        "value": value,
+        "unit": "cell*ordinate*steps/s",
+        "n_gpus": 1,
+        "steps": S,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / S,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": spec.name, "grid": "%dx%d" % (nx, ny), "ordinates": spec.M, "time_steps": spec.K,
+                   "combinations": spec.Nq, "beams": len(spec.beams), "detectors": len(spec.detectors),
+                   "path": "batched (combination chunks of %d per launch)" % chunk,
+                   "states": "checkpoints every %d steps, segments replayed in the adjoint" % ckpt,
+                   "step": "one of %d equal operation ranges of the gradient (%d operations); the %d timed "
+                           "steps are one whole gradient" % (S, n_ops, S),
+                   "launch": "eager, one stream", "workspace_GB": round(ws_gb, 1), "schedule": sched,
+                   "units_per_gradient": units},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS,
+                     "traffic": None if traffic is None else traffic["bytes"],
+                     "kernel": dom, "algorithmic_bytes_per_unit": ALGO_WORDS[dom] * word,
+                     "units_per_launch": upl, "algorithmic_bytes_per_launch": algo_bytes,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
+                     "traffic_over_algorithmic": None if traffic is None else round(traffic["bytes"] / algo_bytes, 3),
+                     "timing": "HIP events around a graph of 20 back-to-back launches per kernel class on the "
+                               "plan's stream, after the timed steps"},
+        "path_roofline": {"algorithmic_bytes_per_unit": PATH_WORDS_REPLAY * word,
+                          "note": "forward 6 + replay 6 + adjoint 6 words + 1 stored state per unit",
+                          "achieved_GB_s": path_gbs, "frac": path_gbs / HBM_PEAK_GBS},
+        "kernels": kernels,
+        "plain": plain,
+        "batched_over_plain": None if plain is None else value / plain["value"],
+    }
+    if not args.no_cpu_baseline:
+        one = spec.with_(beams=[dataclasses.replace(b, group=0) for b in spec.beams if b.group == 0])
+        what = "one of the %d combinations on the full %dx%d grid, %d ordinates" % (spec.Nq, nx, ny, spec.M)
+        log_fn("bench: timing the CPU oracle on a bounded sample (1 thread)")
+        single = cpu_baseline_sample(one, args.cpu_seconds, 1, what)
+        nc = host_cores()
+        if nc > 1:
+            log_fn("bench: timing the CPU oracle on a bounded sample (%d threads)" % nc)
+            out["cpu_baseline"] = cpu_baseline_sample(one, args.cpu_seconds, nc, what)
+            out["cpu_baseline"]["one_thread"] = {"value": single["value"], "sample": single["sample"]}
+        else:
+            out["cpu_baseline"] = single
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -508,9 +744,9 @@ def main():
                     help='fixed launch schedule instead of autotuning, e.g. \'{"line_units_per_wave": 1, "line_waves_per_unit": 2}\'')
     ap.add_argument("--tune-cache", default=None, metavar="JSON",
                     help="autotuner cache file (reuse one tuned schedule across runs, e.g. profiler passes)")
-    ap.add_argument("--uneven-scale", type=float, default=0.5,
+    ap.add_argument("--uneven-scale", type=float, default=0.0,
                     help="grid and step scale of the uneven-batch comparison (0 skips it)")
-    ap.add_argument("--mss-steps", type=int, default=150,
+    ap.add_argument("--mss-steps", type=int, default=0,
                     help="time steps of the batched-vs-plain MSS comparison (0 skips it)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one eager gradient only (no graph, no events): the command profiled for counters")
@@ -521,12 +757,18 @@ def main():
     ap.add_argument("--inverse-beams", type=int, default=8, help="with --workload inverse: beams on the perimeter")
     ap.add_argument("--inverse-combinations", type=int, default=2, help="with --workload inverse: MSS combinations")
     ap.add_argument("--inverse-spacing", type=float, default=40.0, help="with --workload inverse: MSS delay step (ps)")
-    ap.add_argument("--workload", choices=["gradient", "mss-full", "neck", "inverse", "mms", "lab-flux", "uneven-full"], default="gradient",
-                    help="gradient (default): the benchmark line; mss-full / neck: one full-size gradient of the "
-                         "MSS or neck-phantom workload, batched and plain (prints its own JSON line)")
+    ap.add_argument("--workload", choices=["mss", "gradient257", "mss-full", "neck", "inverse", "mms", "lab-flux",
+                                           "uneven-full"], default="mss",
+                    help="mss (default): the benchmark line (batched MSS gradient, 513 x 513 x 64, 8 combinations, "
+                         "6000 steps, checkpointed; a step is one slice of it); gradient257: the 257 x 257 x 32, "
+                         "2000-step single-source gradient (a step is one whole gradient, graph replay); mss-full / "
+                         "neck: one full-size gradient, batched and plain, FP64 and FP32 (own JSON line)")
     ap.add_argument("--workload-steps", type=int, default=0,
-                    help="with --workload mss-full/neck: run only the first K steps (0 = all)")
-    ap.add_argument("--no-plain", action="store_true", help="with --workload mss-full/neck: skip the plain run")
+                    help="with --workload mss/mss-full/neck: run only the first K time steps (0 = all)")
+    ap.add_argument("--no-plain", action="store_true", help="with --workload mss/mss-full/neck: skip the plain run")
+    ap.add_argument("--combo-chunk", type=int, default=0,
+                    help="with --workload mss: combinations per chunk (0 = as many as fit in 85 %% of free HBM); "
+                         "profiling runs pin the chunk of the full run so kernel shapes match")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -562,7 +804,12 @@ def main():
         print(json.dumps(inverse_workload(args.inverse_n, args.inverse_iters, log, args.inverse_beams,
                                           args.inverse_combinations, args.inverse_spacing)), flush=True)
         return
-    if args.workload != "gradient":
+    if args.workload == "mss":
+        out = mss_headline(args, log)
+        if out is not None:
+            print(json.dumps(out), flush=True)
+        return
+    if args.workload != "gradient257":
         dts = ["f64", "f32"] if args.workload == "mss-full" else ["f32"]
         out = full_workload(args.workload, dts, args.workload_steps, log, plain=not args.no_plain)
         print(json.dumps(out), flush=True)
@@ -663,7 +910,7 @@ def main():
     ach = kernels[dom]["GB_s"]
     path_gbs = value * PATH_WORDS_STORE_ALL * word / 1e9
     bytes_per_launch = KERNEL_WORDS[dom] * word * units_per_launch
-    traffic = measured_traffic(args.dtype, dom)
+    traffic = measured_traffic("gradient257", args.dtype, dom)
     out = {
         "metric": "cell*ordinate*steps/s fwd+adjoint on 1 GPU, batched vs plain, at rel-L2 1e-10",
         "value": value,

@@ -96,7 +96,7 @@ CASES = [
     dict(N=12, M=80, K=6, seed=10, n_in=1.33),              # 5 row tiles (runtime tile count)
     dict(N=64, M=16, K=10, seed=11, Ny=20, n_in=1.4),       # four-step x lines, generic y lines
     dict(N=128, M=8, K=6, seed=12, n_in=1.4),               # N_p = 160 (16 x 10 split)
-    dict(N=1024, M=4, K=6, seed=13, Ny=9, n_in=1.4),        # x lines N_p = 1080 (generic kernel)
+    dict(N=1024, M=4, K=6, seed=13, Ny=9, n_in=1.4),        # x lines N_p = 1080 (long four-step variant)
     dict(N=9, M=8, K=6, seed=14, Ny=700, n_in=1.33),        # y lines N_p = 729 = 3^6 (generic)
 ]
 GRAD_CASES = [0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 12, 13]
@@ -249,8 +249,8 @@ def test_gradient_workload_full_size_spot_checks(rte):
     Gs, uKs = plan_s.forward(a, b, want_u_final=True)
     say("  first %d steps: u %.2e  G %.2e (|G| max %.1e)" % (Ks, rel(uKs.cpu(), uK_o), rel(Gs.cpu(), G_o) if np.abs(G_o).max() > 0 else 0.0, np.abs(G_o).max()))
     assert rel(uKs.cpu(), uK_o) < TOL64
-    # the detectors are dark in the first steps: G only has to vanish with the oracle's
-    assert np.abs(Gs.cpu().numpy() - G_o).max() <= 1e-10 * max(np.abs(G_o).max(), np.abs(uK_o).max())
+    # (G of this run is compared element by element over 300 lit steps in
+    # tests/test_gpu_fullsize.py; here the detectors are still dark)
     # directional derivative of J along a smooth perturbation
     rng = np.random.default_rng(5)
     X, Y = np.meshgrid(np.linspace(0, 1, spec.Nx + 1), np.linspace(0, 1, spec.Ny + 1))
@@ -271,19 +271,9 @@ def test_neck_phantom_first_steps(rte):
     # first 3 steps, FP64 and FP32 against the FP64 oracle
     import dataclasses
     full = W.neck_phantom()
-    spec = full.with_(K=3, beams=[dataclasses.replace(b, group=0) for b in full.beams if b.group == 0])
+    spec = full.with_(K=3, beams=[dataclasses.replace(b, group=0, tau=0.0, t0=0.0) for b in full.beams if b.group == 0])
     say("neck first steps", spec.Nx + 1, spec.M, spec.K)
-    G_o, uK_o, _ = Oracle(spec).forward()
-    scale = max(np.abs(G_o).max(), np.abs(uK_o).max())
-    for dt, bar in ((torch.float64, TOL64), (torch.float32, TOL32)):
-        plan = rte.Plan(spec, dt)
-        assert plan.Np_x == 1080 and plan.Np_y == 1080
-        G, uK = plan.forward(spec.mu_a, spec.mu_s, want_u_final=True)
-        torch.cuda.synchronize()
-        eu, eg = rel(uK.cpu(), uK_o), np.abs(G.cpu().numpy() - G_o).max() / scale
-        say("  %s: u %.2e  G (max abs / state max) %.2e" % (dt, eu, eg))
-        assert eu < bar and eg < bar
-        plan.close()
+    _first_steps_check(rte, spec, Np=1080)
 
 
 def test_mss_workload_first_steps(rte):
@@ -293,19 +283,10 @@ def test_mss_workload_first_steps(rte):
     import dataclasses
     full = W.config(2)
     keep = {0: 0, 5: 1}
-    spec = full.with_(K=3, beams=[dataclasses.replace(b, group=keep[b.group]) for b in full.beams if b.group in keep])
+    spec = full.with_(K=3, beams=[dataclasses.replace(b, group=keep[b.group], tau=0.0, t0=0.0)
+                                  for b in full.beams if b.group in keep])
     say("mss first steps", spec.Nx + 1, spec.M, spec.Nq, spec.K)
-    G_o, uK_o, _ = Oracle(spec).forward()
-    scale = max(np.abs(G_o).max(), np.abs(uK_o).max())
-    for dt, bar in ((torch.float64, TOL64), (torch.float32, TOL32)):
-        plan = rte.Plan(spec, dt)
-        assert plan.Np_x == 540 and plan.Nq == 2
-        G, uK = plan.forward(spec.mu_a, spec.mu_s, want_u_final=True)
-        torch.cuda.synchronize()
-        eu, eg = rel(uK.cpu(), uK_o), np.abs(G.cpu().numpy() - G_o).max() / scale
-        say("  %s: u %.2e  G (max abs / state max) %.2e" % (dt, eu, eg))
-        assert eu < bar and eg < bar
-        plan.close()
+    _first_steps_check(rte, spec, Np=540, Nq=2)
 
 
 @pytest.mark.parametrize("idx", [4, 9])
@@ -313,15 +294,30 @@ def test_uneven_instances_first_steps(rte, idx):
     # full-size instances of the uneven batch with 48 ordinates (3 row tiles
     # of 16 slots) on their own grids (330 and 481 nodes per side: N_p = 360
     # and 512), the first 3 steps, FP64 and FP32 against the FP64 oracle
-    spec = W.uneven_batch()[idx].with_(K=3)
+    import dataclasses
+    full = W.uneven_batch()[idx]
+    spec = full.with_(K=3, beams=[dataclasses.replace(b, tau=0.0, t0=0.0) for b in full.beams])
     say("uneven instance", idx, spec.Nx + 1, spec.M)
+    _first_steps_check(rte, spec)
+
+
+def _first_steps_check(rte, spec, Np=None, Nq=None):
+    """u^K by relative L2 to 1e-10 (1e-5 FP32); G by relative L2 against
+    the oracle's G, within max(1e-10, 4 x floor) in FP64 (the pulses are
+    moved to the start so that the detectors are lit)."""
     G_o, uK_o, _ = Oracle(spec).forward()
-    scale = max(np.abs(G_o).max(), np.abs(uK_o).max())
+    fG, _ = floor_forward(spec)
+    assert np.linalg.norm(G_o) > 0
     for dt, bar in ((torch.float64, TOL64), (torch.float32, TOL32)):
         plan = rte.Plan(spec, dt)
+        if Np is not None:
+            assert plan.Np_x == Np and plan.Np_y == Np
+        if Nq is not None:
+            assert plan.Nq == Nq
         G, uK = plan.forward(spec.mu_a, spec.mu_s, want_u_final=True)
         torch.cuda.synchronize()
-        eu, eg = rel(uK.cpu(), uK_o), np.abs(G.cpu().numpy() - G_o).max() / scale
-        say("  %s: N_p %d, u %.2e  G (max abs / state max) %.2e" % (dt, plan.Np_x, eu, eg))
-        assert eu < bar and eg < bar
+        eu, eg = rel(uK.cpu(), uK_o), rel(G.cpu(), G_o)
+        gbar = tol(fG) if dt == torch.float64 else bar
+        say("  %s: N_p %d, u %.2e  G %.2e (floor %.2e)" % (dt, plan.Np_x, eu, eg, fG))
+        assert eu < bar and eg < gbar, (eu, eg, gbar)
         plan.close()
