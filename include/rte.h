@@ -149,6 +149,22 @@ int rte_workspace_bytes(const rte_plan* plan, int with_adjoint, int64_t* bytes);
 int rte_forward(rte_plan* plan, const void* mu_a, const void* mu_s, double* G, void* u_final,
                 int save_states, void* workspace, int64_t workspace_bytes, void* stream);
 
+/* rte_forward (no kept states) without a workspace argument, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  The workspace lives in a
+ * static device array of 128 MiB that each GPU the library runs on holds
+ * until the process ends; its address is resolved once per device on the
+ * first call there.  The call allocates nothing (no hipMalloc, no events);
+ * everything the forward needs at zero is cleared by the call itself, the
+ * rest keeps the previous call's contents.  Calls that overlap on one GPU
+ * (two streams, or two threads) share the array and race: serialize them.
+ * A forward saved by rte_forward / rte_gradient in a caller workspace stays
+ * valid.  Same arguments and outputs as rte_forward with save_states = 0.
+ * RTE_ENOMEM when rte_workspace_bytes(plan, 0) exceeds 128 MiB, before any
+ * device work (the 257 x 257-node, 32-ordinate, 2000-step FP64 forward needs
+ * 136 MB; with 28 ordinates it fits).                                      */
+int rte_forward_noalloc(rte_plan* plan, const void* mu_a, const void* mu_s, double* G, void* u_final, void* stream);
+
 /* Exact discrete adjoint of the last rte_forward(save_states=1) made with the
  * same workspace and medium (discrete image of eq. (AdjointProblem)).
  *   G_bar      : device, double [Nq][Nd][K], the cotangent dJ/dG

@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librte.so")
 SOURCES = ["plan.cpp", "capi.cpp", "line_kernels.hip", "line4_kernels.hip", "line4_extra0.hip", "line4_extra1.hip",
-           "line4_extra2.hip", "line4_extra3.hip", "line4_long0.hip", "line4_long1.hip", "node_kernels.hip"]
+           "line4_extra2.hip", "line4_extra3.hip", "line4_long0.hip", "line4_long1.hip", "node_kernels.hip",
+           "noalloc.cpp"]
 ARCH = os.environ.get("RTE_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
