@@ -787,7 +787,9 @@ int autotune(Plan& p, const void* mu_a, const void* mu_s, void* wsp, int64_t wsb
     for (int upw : {2, 1})
       for (int nw : {1, 2})
         for (int tg : {0, 1}) line_cands.push_back({upw, nw, 0, tg});
-  line_cands.push_back({1, 1, 1, 0});
+  // the generic kernel transforms two ordinates of one line as one complex
+  // line (less accurate near beams): a candidate only without a split
+  if (!four) line_cands.push_back({1, 1, 1, 0});
   double best_ms = 1e30;
   for (const auto& c : line_cands) {
     p.sched.line_units_per_wave = c.upw;

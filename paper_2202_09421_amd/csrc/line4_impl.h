@@ -14,9 +14,17 @@
 // Each transform is a compile-time codelet held in registers, so a line makes
 // three LDS round trips.
 //
-// Work unit: two neighbouring lines of one ordinate group (four complex
-// lines: slots r0 + i r1 and r2 + i r3 of each line, differentiated together
-// since the operator is real-linear).  A workgroup is one wave and handles
+// Work unit: two neighbouring lines of one ordinate group, four complex
+// lines: complex line r holds slot r of the first line in its real part and
+// slot r of the second in its imaginary part (the operator is real-linear, so
+// both are differentiated by one complex transform).  Pairing one ordinate of
+// two neighbouring lines keeps the rounding of each relative to values of
+// similar size; pairing two ordinates of one line (a bright and a dim one,
+// near a beam) makes the dim one's derivative inherit the bright one's
+// rounding, which grew the gradient maps' error 4x at 513 x 513 x 64.
+// Loads and stores keep one lane per (point, line): the two lanes of a pair
+// hold the same point of the two lines and swap two values each (DPP, no
+// LDS) to form or split full complex entries.  A workgroup is one wave and handles
 // two consecutive units; every global load of both units, and of the FC
 // tables, is issued before the first one is transformed, so the memory
 // latency is paid once per wave.  x units come first, then y units; unit
@@ -44,7 +52,7 @@ struct Lines4Args {
   int nunits;
 };
 
-constexpr int kLP = 4;  // complex lines per unit (two lines x slot pairs)
+constexpr int kLP = 4;  // complex lines per unit (slot r of both lines, r = 0..3)
 
 // One unit per workgroup: workgroup b runs on XCD b % 8, so units 2x and
 // 2x + 1 of each chunk of 16 (the two column pairs of one 128-byte row
@@ -120,9 +128,12 @@ __device__ __forceinline__ void load_unit(const Lines4Args<T>& a, const UnitDesc
   }
 }
 
-// LDS layout (doubles): buf [kLP][LSZ] complex (rows of N2 + 1 entries, line
-// stride LSZ = 2 mod 4 entries so that the two lines stored by neighbouring
-// lanes fall in different bank halves) | roots, complex, entry e at e + e / 16
+// LDS layout (doubles): buf [kLP][LSZ] complex (rows of PS entries, PS the
+// smallest odd count >= N2: step B's lanes read rows PS apart, and an odd
+// stride of 16-byte entries spreads 16 consecutive lanes over distinct
+// banks; line stride LSZ = 2 mod 4 entries so that the two complex lines
+// stored by neighbouring lanes fall in different bank halves) | roots,
+// complex, entry e at e + e / 16
 // (spreads the strided twiddle reads over the banks) | mu [N] | continuation
 // matrix [(C+E) x 2d].  The transpose keeps its 2d fold values per line in
 // the line's own extension region (positions n .. n + 2d - 1, free once the
@@ -130,7 +141,7 @@ __device__ __forceinline__ void load_unit(const Lines4Args<T>& a, const UnitDesc
 template <int N1, int N2>
 struct L4Smem {
   static constexpr int N = N1 * N2;
-  static constexpr int PS = N2 + 1;
+  static constexpr int PS = N2 | 1;
   static constexpr int LSZ0 = N1 * PS;
   static constexpr int LSZ = LSZ0 + (6 - LSZ0 % 4) % 4;
   static constexpr int NR = N + N / 16 + 1;
@@ -162,6 +173,30 @@ inline size_t l4_lds_bytes(const FcPlanDev& fc) {
 
 __device__ __forceinline__ int rix(int e) { return e + (e >> 4); }
 
+// Value of the neighbouring lane (lane ^ 1) of a lane pair: DPP quad
+// permutation [1, 0, 3, 2] on the two 32-bit halves.  Both lanes of every
+// pair must be active.
+__device__ __forceinline__ double pair_swap(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Staging of one (point, line) lane: x = its 4 slots (scaled), it = its line.
+// Writes complex lines 2 it and 2 it + 1 at LDS position ph: line r holds
+// {first line's slot r, second line's slot r}.
+__device__ __forceinline__ void stage_pair(cx<double>* buf, int LSZ, int ph, int it, const double* x) {
+  const bool odd = it != 0;
+  const double r0 = pair_swap(odd ? x[0] : x[2]);
+  const double r1 = pair_swap(odd ? x[1] : x[3]);
+  // it = 0: lines 0, 1 = {x0, r0}, {x1, r1}; it = 1: lines 2, 3 = {r0, x2}, {r1, x3}
+  const cx<double> a = {odd ? r0 : x[0], odd ? x[2] : r0};
+  const cx<double> b = {odd ? r1 : x[1], odd ? x[3] : r1};
+  buf[(2 * it) * LSZ + ph] = a;
+  buf[(2 * it + 1) * LSZ + ph] = b;
+}
+
 template <typename T, int TMAX, int N1, int N2, int NTH>
 __device__ __forceinline__ void stage_unit(const UnitRegs<T, TMAX>& R, const UnitDesc& d, const double* coef,
                                            bool adj, int n, int tid, cx<double>* buf) {
@@ -172,10 +207,12 @@ __device__ __forceinline__ void stage_unit(const UnitRegs<T, TMAX>& R, const Uni
 #pragma unroll
   for (int t = 0; t < TMAX; ++t) {
     const int e = tid + NTH * t, it = e & 1, i = e >> 1;
-    if (i < n) {
+    if (i < n) {   // both lanes of a pair have the same point i
       const int ph = (i / N2) * SM::PS + i % N2;
-      buf[(2 * it) * SM::LSZ + ph] = {cf[0] * (double)R.v[t][0], cf[1] * (double)R.v[t][1]};
-      buf[(2 * it + 1) * SM::LSZ + ph] = {cf[2] * (double)R.v[t][2], cf[3] * (double)R.v[t][3]};
+      double x[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) x[r] = cf[r] * (double)R.v[t][r];
+      stage_pair(buf, SM::LSZ, ph, it, x);
     }
   }
   if (adj) {
@@ -311,21 +348,28 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
 #pragma unroll
   for (int t = 0; t < TMAX; ++t) {
     const int e = tid + NTH * t, it = e & 1, i = e >> 1;
-    if (i < n && (it == 0 || d.has1)) {
-      const cx<double> z0 = buf[(2 * it) * LSZ + ph(i)], z1 = buf[(2 * it + 1) * LSZ + ph(i)];
-      double dv[4] = {z0.re, z0.im, z1.re, z1.im};
+    if (i < n) {   // both lanes of a pair have the same point i
+      // complex lines 2 it, 2 it + 1 of this point (plus the fold), then the
+      // lane's own line: two slots from its entries, two from its partner's
+      cx<double> z0 = buf[(2 * it) * LSZ + ph(i)], z1 = buf[(2 * it + 1) * LSZ + ph(i)];
       if (ADJ) {
         if (i >= n - dd) {
           const int fp = ph(n + (i - (n - dd)));
-          const cx<double> f0 = buf[(2 * it) * LSZ + fp], f1 = buf[(2 * it + 1) * LSZ + fp];
-          dv[0] += f0.re; dv[1] += f0.im; dv[2] += f1.re; dv[3] += f1.im;
+          z0 = cx_add(z0, buf[(2 * it) * LSZ + fp]);
+          z1 = cx_add(z1, buf[(2 * it + 1) * LSZ + fp]);
         }
         if (i < dd) {
           const int fp = ph(n + dd + (dd - 1 - i));
-          const cx<double> f0 = buf[(2 * it) * LSZ + fp], f1 = buf[(2 * it + 1) * LSZ + fp];
-          dv[0] += f0.re; dv[1] += f0.im; dv[2] += f1.re; dv[3] += f1.im;
+          z0 = cx_add(z0, buf[(2 * it) * LSZ + fp]);
+          z1 = cx_add(z1, buf[(2 * it + 1) * LSZ + fp]);
         }
       }
+      const bool odd = it != 0;
+      const double r0 = pair_swap(odd ? z0.re : z0.im);
+      const double r1 = pair_swap(odd ? z1.re : z1.im);
+      // it = 0: {z0.re, z1.re, r0, r1}; it = 1: {r0, r1, z0.im, z1.im}
+      const double dv[4] = {odd ? r0 : z0.re, odd ? r1 : z1.re, odd ? z0.im : r0, odd ? z1.im : r1};
+      if (it == 1 && !d.has1) continue;
       T* q = out + it * ls + (int64_t)i * ps;
       if constexpr (sizeof(T) == 8) {
         reinterpret_cast<double2*>(q)[0] = make_double2(c4[0] * dv[0], c4[1] * dv[1]);
@@ -473,10 +517,10 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
         const int e = tid + NTH * (c0 + t), it = e & 1, i = e >> 1;
         if (c0 + t < TMAX && i < n) {
           const int ph = (i / N2) * SM::PS + i % N2;
-          const double f0 = ADJ ? cf[d0.s0] : 1.0, f1 = ADJ ? cf[d0.s0 + 1] : 1.0;
-          const double f2 = ADJ ? cf[d0.s0 + 2] : 1.0, f3 = ADJ ? cf[d0.s0 + 3] : 1.0;
-          buf[(2 * it) * SM::LSZ + ph] = {f0 * (double)R.v[t][0], f1 * (double)R.v[t][1]};
-          buf[(2 * it + 1) * SM::LSZ + ph] = {f2 * (double)R.v[t][2], f3 * (double)R.v[t][3]};
+          double x[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) x[r] = (ADJ ? cf[d0.s0 + r] : 1.0) * (double)R.v[t][r];
+          stage_pair(buf, SM::LSZ, ph, it, x);
         }
       }
     }
