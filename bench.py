@@ -62,8 +62,7 @@ TRAFFIC_ROWS = {
     "lines_fwd": "x and y line derivatives (fwd)", "node_fwd": "node pass (fwd)",
     "node_adj": "node pass (adj)", "lines_adj": "x and y line transposes (adj)",
 }
-TRAFFIC_FILE = {("gradient257", "f64"): "profiles/gradient_fp64_257x257_M32_K2000_hbm_traffic.md",
-                ("mss", "f64"): "profiles/mss_fp64_513x513_M64_chunk4_hbm_traffic.md"}
+TRAFFIC_FILE = {("mss", "f64"): "profiles/mss_fp64_513x513_M64_chunk4_hbm_traffic.md"}
 
 
 def source_hash():
@@ -620,6 +619,11 @@ def mss_headline(args, log_fn):
         plan.gradient_range(a_bg, b_bg, Gm, cuts[k % S], cuts[k % S + 1])
         torch.cuda.synchronize()
         log_fn("bench: warmup slice %d done" % k)
+    # per-kernel durations over the timed region: HIP events around every
+    # launch of the four per-step kernel classes, on the plan's stream
+    events = not args.no_kernel_events
+    if events:
+        rte.profile_enable(plan, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(S):
@@ -628,13 +632,21 @@ def mss_headline(args, log_fn):
             log_fn("bench: slice %d of %d enqueued" % (k, S))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    live = rte.profile_read(plan) if events else None
+    rte.profile_enable(plan, False)
     Jb, gab, gbb = (x.clone() for x in out[:3])
     log_fn("bench: batched gradient in %d slices: %.2f s (J = %.6e)" % (S, elapsed, float(Jb.item())))
     if not np.isfinite(float(Jb.item())) or not torch.isfinite(gab).all():
         raise RuntimeError("non-finite gradient")
     reps = 20
-    kus = plan.time_kernels(a_bg, b_bg, reps=reps)
-    log_fn("bench: per-launch kernel times (us) %s" % {k: round(v, 1) for k, v in kus.items()})
+    kus_graph = plan.time_kernels(a_bg, b_bg, reps=reps)
+    log_fn("bench: per-launch kernel times, graph of %d launches (us) %s" % (
+        reps, {k: round(v, 1) for k, v in kus_graph.items()}))
+    if live:
+        kus = {k: 1000.0 * ms / n for k, (ms, n) in live.items() if n > 0}
+        log_fn("bench: per-launch kernel times over the timed region (us) %s" % {k: round(v, 1) for k, v in kus.items()})
+    else:
+        kus = kus_graph
     plan.close()
     del plan, out
     torch.cuda.empty_cache()
@@ -667,7 +679,9 @@ def mss_headline(args, log_fn):
     word = WORD[args.dtype]
     kernels = {}
     for cls, us in kus.items():
-        kernels[cls] = {"avg_us": round(us, 2), "launches_per_gradient": per_grad[cls],
+        kernels[cls] = {"avg_us": round(us, 2), "graph_avg_us": round(kus_graph[cls], 2),
+                        "launches_timed": None if not live else live[cls][1],
+                        "launches_per_gradient": per_grad[cls],
                         "ms_per_gradient": round(us * per_grad[cls] / 1000.0, 1),
                         "algorithmic_GB_s": round(ALGO_WORDS[cls] * word * upl / (us * 1e-6) / 1e9, 1),
                         "compulsory_GB_s": round(KERNEL_WORDS[cls] * word * upl / (us * 1e-6) / 1e9, 1)}
@@ -708,8 +722,9 @@ def mss_headline(args, log_fn):
                      "units_per_launch": upl, "algorithmic_bytes_per_launch": algo_bytes,
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
                      "traffic_over_algorithmic": None if traffic is None else round(traffic["bytes"] / algo_bytes, 3),
-                     "timing": "HIP events around a graph of 20 back-to-back launches per kernel class on the "
-                               "plan's stream, after the timed steps"},
+                     "timing": ("HIP events around every launch of the kernel class on the plan's stream over "
+                                "the timed steps" if live else "HIP events around a graph of 20 back-to-back "
+                                "launches per kernel class on the plan's stream, after the timed steps")},
         "path_roofline": {"algorithmic_bytes_per_unit": PATH_WORDS_REPLAY * word,
                           "note": "forward 6 + replay 6 + adjoint 6 words + 1 stored state per unit",
                           "achieved_GB_s": path_gbs, "frac": path_gbs / HBM_PEAK_GBS},
@@ -766,6 +781,9 @@ def main():
     ap.add_argument("--workload-steps", type=int, default=0,
                     help="with --workload mss/mss-full/neck: run only the first K time steps (0 = all)")
     ap.add_argument("--no-plain", action="store_true", help="with --workload mss/mss-full/neck: skip the plain run")
+    ap.add_argument("--no-kernel-events", action="store_true",
+                    help="with --workload mss: no HIP events around the timed launches (kernel durations then "
+                         "come from graph replays after the timed steps)")
     ap.add_argument("--combo-chunk", type=int, default=0,
                     help="with --workload mss: combinations per chunk (0 = as many as fit in 85 %% of free HBM); "
                          "profiling runs pin the chunk of the full run so kernel shapes match")
