@@ -98,8 +98,14 @@ CASES = [
     dict(N=128, M=8, K=6, seed=12, n_in=1.4),               # N_p = 160 (16 x 10 split)
     dict(N=1024, M=4, K=6, seed=13, Ny=9, n_in=1.4),        # x lines N_p = 1080 (long four-step variant)
     dict(N=9, M=8, K=6, seed=14, Ny=700, n_in=1.33),        # y lines N_p = 729 = 3^6 (generic)
+    # degenerate media: isotropic scattering with an index-matched boundary
+    # (no reflection), no scattering at all, no absorption in a homogeneous
+    # medium
+    dict(N=16, M=8, K=20, seed=15, g=0.0, n_in=1.0),
+    dict(N=16, M=12, K=20, seed=16, b0=0.0, n_in=1.4),
+    dict(N=16, M=8, K=20, seed=17, a0=0.0, heterogeneous=False),
 ]
-GRAD_CASES = [0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 12, 13]
+GRAD_CASES = [0, 1, 2, 3, 4, 5, 7, 8, 9, 10, 12, 13, 14, 15, 16]
 
 
 def _spec(case):
