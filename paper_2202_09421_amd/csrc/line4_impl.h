@@ -224,6 +224,58 @@ __device__ __forceinline__ void stage_unit(const UnitRegs<T, TMAX>& R, const Uni
   }
 }
 
+// Twiddles w^(b k), k = 1 .. K - 1, of the length-N roots table: only the
+// table values w^(b 2^j) are loaded, and every other power is one complex
+// product of an earlier power and one of them, at most log2 K products deep
+// (relative error a few units in the last place).  Loading 5 values instead
+// of K - 1 leaves the vector memory pipe to the state streams.  Used up to
+// kLongLine; the long lines load every twiddle.
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+template <int N, int K>
+struct TwPow {
+  static constexpr int NB = ilog2c(K - 1) + 1;   // powers 2^0 .. 2^(NB-1) <= K - 1
+  cx<double> P[NB];
+  cx<double> w[K];
+  // TG: from the global table; otherwise from the staged copy in LDS (both
+  // paths then do identical arithmetic)
+  template <bool TG>
+  __device__ __forceinline__ void init(const double* groots, const cx<double>* roots, int b) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int e = (b << j) % N;
+      P[j] = TG ? cx<double>{groots[2 * e], groots[2 * e + 1]} : roots[rix(e)];
+    }
+  }
+  template <int k>
+  __device__ __forceinline__ cx<double> get() {
+    constexpr int lb = k & -k;
+    constexpr int j = ilog2c(lb);
+    static_assert(j < NB, "power table too short");
+    if constexpr (k == lb) {
+      w[k] = P[j];
+    } else {
+      const cx<double> a = w[k - lb], p = P[j];
+      w[k] = {a.re * p.re - a.im * p.im, a.re * p.im + a.im * p.re};
+    }
+    return w[k];
+  }
+};
+
+// x[k] *= w^(S b k) for k = k0 .. K - 1 (S = +-1 conjugates)
+template <int N, int K, int k, int S>
+struct TwApply {
+  static __device__ __forceinline__ void run(TwPow<N, K>& tp, cx<double>* x) {
+    const cx<double> w = tp.template get<k>();
+    x[k] = cx_rot(x[k], w.re, S * w.im);
+    TwApply<N, K, k + 1, S>::run(tp, x);
+  }
+};
+template <int N, int K, int S>
+struct TwApply<N, K, K, S> {
+  static __device__ __forceinline__ void run(TwPow<N, K>&, cx<double>*) {}
+};
+
 // Continuation, derivative (or its transpose) and store of one staged unit.
 template <typename T, bool ADJ, int N1, int N2, int NTH, bool TG>
 __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int dd, int CE,
@@ -269,11 +321,17 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
 #pragma unroll
     for (int i = 0; i < N1; ++i) x[i] = buf[l * LSZ + i * PS + n2];
     Dft<N1, -1, double>::run(x);
+    if constexpr (N <= kLongLine) {
+      TwPow<N, N1> tp;
+      tp.template init<TG>(groots, roots, n2);
+      TwApply<N, N1, 1, 1>::run(tp, x);
+    } else {
 #pragma unroll
-    for (int k1 = 1; k1 < N1; ++k1) {
-      const int e = (n2 * k1) % N;
-      const cx<double> w = TG ? cx<double>{groots[2 * e], groots[2 * e + 1]} : roots[rix(e)];
-      x[k1] = cx_rot(x[k1], w.re, w.im);
+      for (int k1 = 1; k1 < N1; ++k1) {
+        const int e = (n2 * k1) % N;
+        const cx<double> w = TG ? cx<double>{groots[2 * e], groots[2 * e + 1]} : roots[rix(e)];
+        x[k1] = cx_rot(x[k1], w.re, w.im);
+      }
     }
 #pragma unroll
     for (int i = 0; i < N1; ++i) buf[l * LSZ + i * PS + n2] = x[i];
@@ -293,11 +351,17 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
       x[k2] = ADJ ? cx<double>{m * X.im, -m * X.re} : cx<double>{-m * X.im, m * X.re};
     }
     Dft<N2, 1, double>::run(x);
+    if constexpr (N <= kLongLine) {
+      TwPow<N, N2> tp;
+      tp.template init<TG>(groots, roots, k1);
+      TwApply<N, N2, 1, -1>::run(tp, x);
+    } else {
 #pragma unroll
-    for (int n2 = 1; n2 < N2; ++n2) {
-      const int e = (n2 * k1) % N;
-      const cx<double> w = TG ? cx<double>{groots[2 * e], groots[2 * e + 1]} : roots[rix(e)];
-      x[n2] = cx_rot(x[n2], w.re, -w.im);
+      for (int n2 = 1; n2 < N2; ++n2) {
+        const int e = (n2 * k1) % N;
+        const cx<double> w = TG ? cx<double>{groots[2 * e], groots[2 * e + 1]} : roots[rix(e)];
+        x[n2] = cx_rot(x[n2], w.re, -w.im);
+      }
     }
 #pragma unroll
     for (int i = 0; i < N2; ++i) buf[l * LSZ + k1 * PS + i] = x[i];
