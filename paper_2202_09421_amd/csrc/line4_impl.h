@@ -149,17 +149,30 @@ struct L4Smem {
   static constexpr int ROOTS = 2 * NR;
   static constexpr int MU = N;
   // nmx = (C + E) * 2d continuation entries staged (0 when read from global
-  // memory); TG: twiddles and multipliers are read from global memory (L1 /
-  // L2) instead of being staged
-  static constexpr int mx_off(bool tg) { return BUF + (tg ? 0 : ROOTS + MU); }
-  static constexpr size_t bytes(int nmx, bool tg) { return sizeof(double) * (size_t)(mx_off(tg) + nmx); }
+  // memory).  TG: the twiddles are read from global memory (L1 / L2) instead
+  // of being staged; mus: the multipliers are staged.
+  static constexpr int mu_off(bool tg) { return BUF + (tg ? 0 : ROOTS); }
+  static constexpr int mx_off(bool tg, bool mus) { return mu_off(tg) + (mus ? MU : 0); }
+  static constexpr size_t bytes(int nmx, bool tg, bool mus) {
+    return sizeof(double) * (size_t)(mx_off(tg, mus) + nmx);
+  }
 };
 
-// The transpose (ADJ) and the long lines read the continuation matrix from
-// global memory; the forward pass of lengths up to kLongLine stages it when
-// it has at most kFcTab entries (and reads it from global memory otherwise).
-template <bool ADJ, int N>
-constexpr bool kMxGlobal = ADJ || N > kLongLine;
+// Derivative multipliers staged in LDS: with staged tables, and with global
+// twiddles in the forward pass up to kLongLine (its N2 multiplier reads per
+// step-B transform then stay off the vector memory pipe, 3 % faster at
+// N_p = 540); the transpose with global twiddles (5 % slower with them
+// staged) and the long lines read them from global memory.
+template <bool TG, int N, bool ADJ>
+constexpr bool kMuStaged = !TG || (N <= kLongLine && !ADJ);
+
+// The transpose (ADJ), the forward pass with global twiddles (whose LDS
+// holds the multipliers instead) and the long lines read the continuation
+// matrix from global memory; the forward pass with staged tables stages it
+// when it has at most kFcTab entries (and reads it from global memory
+// otherwise).
+template <bool ADJ, int N, bool TG>
+constexpr bool kMxGlobal = ADJ || N > kLongLine || TG;
 
 __host__ __device__ inline int l4_staged_mx(const FcPlanDev& fc, bool mx_global) {
   const int nmx = 2 * fc.d * (fc.C + fc.E);
@@ -168,7 +181,7 @@ __host__ __device__ inline int l4_staged_mx(const FcPlanDev& fc, bool mx_global)
 
 template <bool ADJ, int N1, int N2, bool TG>
 inline size_t l4_lds_bytes(const FcPlanDev& fc) {
-  return L4Smem<N1, N2>::bytes(l4_staged_mx(fc, kMxGlobal<ADJ, N1 * N2>), TG);
+  return L4Smem<N1, N2>::bytes(l4_staged_mx(fc, kMxGlobal<ADJ, N1 * N2, TG>), TG, kMuStaged<TG, N1 * N2, ADJ>);
 }
 
 __device__ __forceinline__ int rix(int e) { return e + (e >> 4); }
@@ -346,7 +359,7 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
     Dft<N2, -1, double>::run(x);
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
-      const double m = TG ? gmu[k1 + N1 * k2] : mu[k1 + N1 * k2];
+      const double m = kMuStaged<TG, N, ADJ> ? mu[k1 + N1 * k2] : gmu[k1 + N1 * k2];
       const cx<double> X = x[k2];
       x[k2] = ADJ ? cx<double>{m * X.im, -m * X.re} : cx<double>{-m * X.im, m * X.re};
     }
@@ -448,9 +461,9 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
 
 // Issue the loads of the FC tables into registers (kept until staged).
 // MXG: the continuation matrix stays in global memory (long lines).
-template <int N, int NTH, bool TG, bool MXG>
+template <int N, int NTH, bool TG, bool MXG, bool MUS>
 struct TabRegs {
-  static constexpr int RT = TG ? 1 : (N + NTH - 1) / NTH, MT = TG ? 1 : (N + NTH - 1) / NTH,
+  static constexpr int RT = TG ? 1 : (N + NTH - 1) / NTH, MT = MUS ? (N + NTH - 1) / NTH : 1,
                        XT = MXG ? 1 : (kFcTab + NTH - 1) / NTH;
   double rr[RT][2], mm[MT], xx[XT];
   __device__ __forceinline__ void load(const FcPlanDev& fc, int lane) {
@@ -462,6 +475,8 @@ struct TabRegs {
         rr[t][0] = (k < N) ? fc.roots[2 * k] : 0.0;
         rr[t][1] = (k < N) ? fc.roots[2 * k + 1] : 0.0;
       }
+    }
+    if (MUS) {
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         const int k = lane + NTH * t;
@@ -483,6 +498,8 @@ struct TabRegs {
         const int k = lane + NTH * t;
         if (k < N) roots[rix(k)] = {rr[t][0], rr[t][1]};
       }
+    }
+    if (MUS) {
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         const int k = lane + NTH * t;
@@ -509,14 +526,15 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
   constexpr int N = N1 * N2;
   constexpr int NTH = 64 * NW;
   constexpr int TMAX = (2 * N + NTH - 1) / NTH;
-  constexpr bool MXG = kMxGlobal<ADJ, N>;
+  constexpr bool MXG = kMxGlobal<ADJ, N, TG>;
+  constexpr bool MUS = kMuStaged<TG, N, ADJ>;
   typedef L4Smem<N1, N2> SM;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sm = reinterpret_cast<double*>(smem_raw);
   cx<double>* buf = reinterpret_cast<cx<double>*>(sm);
   cx<double>* roots = reinterpret_cast<cx<double>*>(sm + SM::BUF);
-  double* mu = sm + SM::BUF + SM::ROOTS;
-  double* MxS = sm + SM::mx_off(TG);            // staged copy (unused when nmx_st == 0)
+  double* mu = sm + SM::mu_off(TG);
+  double* MxS = sm + SM::mx_off(TG, MUS);       // staged copy (unused when nmx_st == 0)
   const int nmx_st = l4_staged_mx(a.fc, MXG);
   const double* Mx = nmx_st ? MxS : a.fc.Mx;
 
@@ -530,7 +548,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
     UnitRegs<T, TMAX> R0, R1;
     load_unit<T, TMAX, NTH>(a, d0, n, tid, R0);
     load_unit<T, TMAX, NTH>(a, d1, n, tid, R1);
-    TabRegs<N, NTH, TG, MXG> tab;
+    TabRegs<N, NTH, TG, MXG, MUS> tab;
     tab.load(fc, tid);
     tab.stage(roots, mu, MxS, nmx_st, tid);
     if (d0.live) {
@@ -548,7 +566,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
     const UnitDesc d0 = decode_unit(a, remap_unit16((int)blockIdx.x));
     if (!d0.live) return;
     {
-      TabRegs<N, NTH, TG, MXG> tab;
+      TabRegs<N, NTH, TG, MXG, MUS> tab;
       tab.load(fc, tid);
       tab.stage(roots, mu, MxS, nmx_st, tid);
     }
