@@ -507,6 +507,15 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
   const T A = t.valid ? a.mu_a[gn] : T(0), B = t.valid ? a.mu_s[gn] : T(0);
   T af[RTC > 0 ? 4 * RTC : 1];
   load_afrag<T, RTC>(af, a.Wt, G, t);
+  // the node's gradient-map entries, read with the state by the one lane
+  // per node that updates them at the end (no load round trip after the
+  // reduction); each (source, node) belongs to one block of the launch
+  const bool gw = t.rt == 0 && t.r == 0 && t.valid;
+  double ga0 = 0.0, gb0 = 0.0;
+  if (gw) {
+    ga0 = a.ga[(int64_t)q * Nn + gn];
+    gb0 = a.gb[(int64_t)q * Nn + gn];
+  }
 
   // ubar^{n+1}, then v^{n+1} = P^T ubar^{n+1} on boundary nodes
   const double cdt = a.cdt;
@@ -606,8 +615,8 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
   } else if (t.r != 0 || !t.valid) {
     return;
   }
-  a.ga[(int64_t)q * Nn + gn] -= cdt * pa;
-  a.gb[(int64_t)q * Nn + gn] += cdt * pb;
+  a.ga[(int64_t)q * Nn + gn] = ga0 - cdt * pa;
+  a.gb[(int64_t)q * Nn + gn] = gb0 + cdt * pb;
 }
 
 // ---------------------------------------------------------------- launchers
