@@ -166,13 +166,35 @@ struct L4Smem {
 template <bool TG, int N, bool ADJ>
 constexpr bool kMuStaged = !TG || (N <= kLongLine && !ADJ);
 
-// The transpose (ADJ), the forward pass with global twiddles (whose LDS
-// holds the multipliers instead) and the long lines read the continuation
-// matrix from global memory; the forward pass with staged tables stages it
-// when it has at most kFcTab entries (and reads it from global memory
-// otherwise).
+// The forward pass with staged tables stages the continuation matrix
+// ((C + E) x 2d entries) in LDS when it has at most kFcTab entries.  The
+// forward pass with global twiddles (whose LDS holds the multipliers
+// instead) loads each continuation lane's row into registers at the start;
+// the transpose and the long lines read it from global memory (staged, the
+// transpose's fold reads become flat loads of an LDS-or-global pointer and
+// the pass is 8 % slower at N_p = 540).
 template <bool ADJ, int N, bool TG>
 constexpr bool kMxGlobal = ADJ || N > kLongLine || TG;
+
+// Forward pass with global twiddles up to kLongLine: continuation rows in
+// registers, loaded with the unit.
+template <bool ADJ, int N, bool TG>
+constexpr bool kMxPrefetch = !ADJ && TG && N <= kLongLine;
+
+struct MxRows {
+  double mr[kMaxFcD], ml[kMaxFcD];
+  // row `lane` (< C + E) of the continuation matrix: its d right and d left
+  // matching-value coefficients
+  __device__ __forceinline__ void load(const FcPlanDev& fc, int lane) {
+    const int dd = fc.d;
+    const bool on = lane < fc.C + fc.E;
+#pragma unroll
+    for (int k = 0; k < kMaxFcD; ++k) {
+      mr[k] = (on && k < dd) ? fc.Mx[lane * 2 * dd + k] : 0.0;
+      ml[k] = (on && k < dd) ? fc.Mx[lane * 2 * dd + dd + k] : 0.0;
+    }
+  }
+};
 
 __host__ __device__ inline int l4_staged_mx(const FcPlanDev& fc, bool mx_global) {
   const int nmx = 2 * fc.d * (fc.C + fc.E);
@@ -293,7 +315,8 @@ struct TwApply<N, K, K, S> {
 template <typename T, bool ADJ, int N1, int N2, int NTH, bool TG>
 __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int dd, int CE,
                                                int tid, cx<double>* buf, const cx<double>* roots,
-                                               const double* mu, const double* Mx) {
+                                               const double* mu, const double* Mx,
+                                               const MxRows& mxr) {
   const double* __restrict__ groots = a.fc.roots;
   const double* __restrict__ gmu = a.fc.mu;
   typedef L4Smem<N1, N2> SM;
@@ -311,7 +334,9 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
 #pragma unroll
       for (int k = 0; k < kMaxFcD; ++k) {
         if (k < dd) {
-          const double mr = Mx[lane * 2 * dd + k], ml = Mx[lane * 2 * dd + dd + k];
+          constexpr bool PF = kMxPrefetch<ADJ, N1 * N2, TG>;
+          const double mr = PF ? mxr.mr[k] : Mx[lane * 2 * dd + k];
+          const double ml = PF ? mxr.ml[k] : Mx[lane * 2 * dd + dd + k];
 #pragma unroll
           for (int l = 0; l < kLP; ++l) {
             const cx<double> gr = buf[l * LSZ + ph(n - dd + k)];
@@ -541,6 +566,8 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
   const FcPlanDev& fc = a.fc;
   const int n = fc.n, dd = fc.d, CE = fc.C + fc.E;
   const int tid = threadIdx.x;
+  MxRows mxr;
+  if constexpr (kMxPrefetch<ADJ, N, TG>) mxr.load(fc, tid);
 
   if constexpr (UPW == 2) {
     const UnitDesc d0 = decode_unit(a, 2 * (int)blockIdx.x);
@@ -554,13 +581,13 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
     if (d0.live) {
       stage_unit<T, TMAX, N1, N2, NTH>(R0, d0, a.coef[d0.dir], ADJ, n, tid, buf);
       __syncthreads();
-      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, roots, mu, Mx);
+      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, roots, mu, Mx, mxr);
     }
     if (d1.live) {
       __syncthreads();
       stage_unit<T, TMAX, N1, N2, NTH>(R1, d1, a.coef[d1.dir], ADJ, n, tid, buf);
       __syncthreads();
-      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d1, n, dd, CE, tid, buf, roots, mu, Mx);
+      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d1, n, dd, CE, tid, buf, roots, mu, Mx, mxr);
     }
   } else {
     const UnitDesc d0 = decode_unit(a, remap_unit16((int)blockIdx.x));
@@ -614,7 +641,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
       }
     }
     __syncthreads();
-    transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, roots, mu, Mx);
+    transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, roots, mu, Mx, mxr);
   }
 }
 
