@@ -171,8 +171,9 @@ constexpr bool kMuStaged = !TG || (N <= kLongLine && !ADJ);
 // forward pass with global twiddles (whose LDS holds the multipliers
 // instead) loads each continuation lane's row into registers at the start;
 // the transpose and the long lines read it from global memory (staged, the
-// transpose's fold reads become flat loads of an LDS-or-global pointer and
-// the pass is 8 % slower at N_p = 540).
+// transpose is 9 % slower at N_p = 540).  Reads go through the staged copy
+// or the table, chosen by a uniform flag, so that each is an LDS or a global
+// load (a pointer that may be either compiles to flat loads).
 template <bool ADJ, int N, bool TG>
 constexpr bool kMxGlobal = ADJ || N > kLongLine || TG;
 
@@ -180,6 +181,22 @@ constexpr bool kMxGlobal = ADJ || N > kLongLine || TG;
 // registers, loaded with the unit.
 template <bool ADJ, int N, bool TG>
 constexpr bool kMxPrefetch = !ADJ && TG && N <= kLongLine;
+
+// Continuation-matrix reads through address-space-qualified pointers: the
+// staged copy (LDS) or the table (global memory), selected by a uniform flag.
+typedef __attribute__((address_space(3))) const double* lds_cdptr;
+typedef __attribute__((address_space(1))) const double* glb_cdptr;
+// Mx: the staged copy when staged, else the table (the long lines read
+// through it unqualified: never staged).
+template <int N>
+__device__ __forceinline__ double mx_at(bool staged, const double* MxS, const double* Mx, int i) {
+  if constexpr (N > kLongLine) {
+    return Mx[i];
+  } else {
+    if (staged) return ((lds_cdptr)MxS)[i];
+    return ((glb_cdptr)Mx)[i];
+  }
+}
 
 struct MxRows {
   double mr[kMaxFcD], ml[kMaxFcD];
@@ -315,7 +332,7 @@ struct TwApply<N, K, K, S> {
 template <typename T, bool ADJ, int N1, int N2, int NTH, bool TG>
 __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const UnitDesc& d, int n, int dd, int CE,
                                                int tid, cx<double>* buf, const cx<double>* roots,
-                                               const double* mu, const double* Mx,
+                                               const double* mu, const double* Mx, const double* MxS, bool mx_st,
                                                const MxRows& mxr) {
   const double* __restrict__ groots = a.fc.roots;
   const double* __restrict__ gmu = a.fc.mu;
@@ -335,8 +352,8 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
       for (int k = 0; k < kMaxFcD; ++k) {
         if (k < dd) {
           constexpr bool PF = kMxPrefetch<ADJ, N1 * N2, TG>;
-          const double mr = PF ? mxr.mr[k] : Mx[lane * 2 * dd + k];
-          const double ml = PF ? mxr.ml[k] : Mx[lane * 2 * dd + dd + k];
+          const double mr = PF ? mxr.mr[k] : mx_at<N>(mx_st, MxS, Mx, lane * 2 * dd + k);
+          const double ml = PF ? mxr.ml[k] : mx_at<N>(mx_st, MxS, Mx, lane * 2 * dd + dd + k);
 #pragma unroll
           for (int l = 0; l < kLP; ++l) {
             const cx<double> gr = buf[l * LSZ + ph(n - dd + k)];
@@ -429,7 +446,7 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
     if (act) {
 #pragma unroll 4
       for (int p = 0; p < CE; ++p) {
-        const double mv = Mx[p * 2 * dd + c];
+        const double mv = mx_at<N>(mx_st, MxS, Mx, p * 2 * dd + c);
         const cx<double> y = buf[l * LSZ + ph(n + p)];
         sr += mv * y.re;
         si += mv * y.im;
@@ -562,6 +579,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
   double* MxS = sm + SM::mx_off(TG, MUS);       // staged copy (unused when nmx_st == 0)
   const int nmx_st = l4_staged_mx(a.fc, MXG);
   const double* Mx = nmx_st ? MxS : a.fc.Mx;
+  const bool mx_st = nmx_st != 0;
 
   const FcPlanDev& fc = a.fc;
   const int n = fc.n, dd = fc.d, CE = fc.C + fc.E;
@@ -581,13 +599,13 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
     if (d0.live) {
       stage_unit<T, TMAX, N1, N2, NTH>(R0, d0, a.coef[d0.dir], ADJ, n, tid, buf);
       __syncthreads();
-      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, roots, mu, Mx, mxr);
+      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, roots, mu, Mx, MxS, mx_st, mxr);
     }
     if (d1.live) {
       __syncthreads();
       stage_unit<T, TMAX, N1, N2, NTH>(R1, d1, a.coef[d1.dir], ADJ, n, tid, buf);
       __syncthreads();
-      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d1, n, dd, CE, tid, buf, roots, mu, Mx, mxr);
+      transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d1, n, dd, CE, tid, buf, roots, mu, Mx, MxS, mx_st, mxr);
     }
   } else {
     const UnitDesc d0 = decode_unit(a, remap_unit16((int)blockIdx.x));
@@ -641,7 +659,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
       }
     }
     __syncthreads();
-    transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, roots, mu, Mx, mxr);
+    transform_unit<T, ADJ, N1, N2, NTH, TG>(a, d0, n, dd, CE, tid, buf, roots, mu, Mx, MxS, mx_st, mxr);
   }
 }
 
