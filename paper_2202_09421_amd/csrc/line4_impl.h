@@ -159,12 +159,13 @@ struct L4Smem {
 };
 
 // Derivative multipliers staged in LDS: with staged tables, and with global
-// twiddles in the forward pass up to kLongLine (its N2 multiplier reads per
-// step-B transform then stay off the vector memory pipe, 3 % faster at
-// N_p = 540); the transpose with global twiddles (5 % slower with them
-// staged) and the long lines read them from global memory.
-template <bool TG, int N, bool ADJ>
-constexpr bool kMuStaged = !TG || (N <= kLongLine && !ADJ);
+// twiddles in the FP32 forward pass up to kLongLine (its N2 multiplier reads
+// per step-B transform then stay off the vector memory pipe: 4 % faster at
+// N_p = 540).  With global twiddles the FP64 forward pass (1.5 % faster with
+// the smaller LDS footprint), the transpose (5 % slower with them staged)
+// and the long lines read them from global memory.
+template <typename T, bool TG, int N, bool ADJ>
+constexpr bool kMuStaged = !TG || (sizeof(T) == 4 && N <= kLongLine && !ADJ);
 
 // The forward pass with staged tables stages the continuation matrix
 // ((C + E) x 2d entries) in LDS when it has at most kFcTab entries.  The
@@ -218,9 +219,9 @@ __host__ __device__ inline int l4_staged_mx(const FcPlanDev& fc, bool mx_global)
   return (mx_global || nmx > kFcTab) ? 0 : nmx;
 }
 
-template <bool ADJ, int N1, int N2, bool TG>
+template <typename T, bool ADJ, int N1, int N2, bool TG>
 inline size_t l4_lds_bytes(const FcPlanDev& fc) {
-  return L4Smem<N1, N2>::bytes(l4_staged_mx(fc, kMxGlobal<ADJ, N1 * N2, TG>), TG, kMuStaged<TG, N1 * N2, ADJ>);
+  return L4Smem<N1, N2>::bytes(l4_staged_mx(fc, kMxGlobal<ADJ, N1 * N2, TG>), TG, kMuStaged<T, TG, N1 * N2, ADJ>);
 }
 
 __device__ __forceinline__ int rix(int e) { return e + (e >> 4); }
@@ -401,7 +402,7 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
     Dft<N2, -1, double>::run(x);
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
-      const double m = kMuStaged<TG, N, ADJ> ? mu[k1 + N1 * k2] : gmu[k1 + N1 * k2];
+      const double m = kMuStaged<T, TG, N, ADJ> ? mu[k1 + N1 * k2] : gmu[k1 + N1 * k2];
       const cx<double> X = x[k2];
       x[k2] = ADJ ? cx<double>{m * X.im, -m * X.re} : cx<double>{-m * X.im, m * X.re};
     }
@@ -569,7 +570,7 @@ __global__ __launch_bounds__(64 * NW) void lines4_kernel(Lines4Args<T> a) {
   constexpr int NTH = 64 * NW;
   constexpr int TMAX = (2 * N + NTH - 1) / NTH;
   constexpr bool MXG = kMxGlobal<ADJ, N, TG>;
-  constexpr bool MUS = kMuStaged<TG, N, ADJ>;
+  constexpr bool MUS = kMuStaged<T, TG, N, ADJ>;
   typedef L4Smem<N1, N2> SM;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sm = reinterpret_cast<double*>(smem_raw);
@@ -669,7 +670,7 @@ constexpr bool kPairOk = (2 * N1 * N2 + 64 * NW - 1) / (64 * NW) <= 9;
 
 template <typename T, bool ADJ, int N1, int N2, int NW, bool TG>
 inline hipError_t go_nw(const Lines4Args<T>& a, int upw, hipStream_t s) {
-  const size_t sh = l4_lds_bytes<ADJ, N1, N2, TG>(a.fc);
+  const size_t sh = l4_lds_bytes<T, ADJ, N1, N2, TG>(a.fc);
   if (sh > kLines4MaxLds) return hipErrorNotSupported;
   if constexpr (kPairOk<N1, N2, NW>) {
     if (upw == 2) {
@@ -689,7 +690,7 @@ inline hipError_t go_nw(const Lines4Args<T>& a, int upw, hipStream_t s) {
 // variant instantiated for the lengths outside the fully tuned set.
 template <typename T, bool ADJ, int N1, int N2>
 inline hipError_t go_one(const Lines4Args<T>& a, hipStream_t s) {
-  const size_t sh = l4_lds_bytes<ADJ, N1, N2, true>(a.fc);
+  const size_t sh = l4_lds_bytes<T, ADJ, N1, N2, true>(a.fc);
   if (sh > kLines4MaxLds) return hipErrorNotSupported;
   if (a.nunits == 0) return hipSuccess;
   const int groups = ((a.nunits + 15) / 16) * 16;
@@ -714,7 +715,7 @@ hipError_t lines4_extra3(const Lines4Args<float>& a, bool adj, hipStream_t s);
 template <typename T, bool ADJ, int N1, int N2>
 inline hipError_t go_long(const Lines4Args<T>& a, hipStream_t s) {
   static_assert(N1 * N2 > kLongLine, "long-line variant");
-  const size_t sh = l4_lds_bytes<ADJ, N1, N2, true>(a.fc);
+  const size_t sh = l4_lds_bytes<T, ADJ, N1, N2, true>(a.fc);
   if (sh > kLines4MaxLdsLong) return hipErrorNotSupported;
   if (a.nunits == 0) return hipSuccess;
   const int groups = ((a.nunits + 15) / 16) * 16;
