@@ -52,6 +52,34 @@ struct Lines4Args {
   int nunits;
 };
 
+// Store of one (point, line) lane's 4 slots (lengths up to kLongLine).  NT:
+// with the non-temporal hint (the outputs are not read again by the pass).
+// Measured at N_p = 540: 11 % faster FP32 passes, 1 % faster FP64
+// transposes, but a 5 % slower FP64 forward pass, which keeps ordinary
+// stores.
+typedef double d2v_st __attribute__((ext_vector_type(2)));
+typedef float f4v_st __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ void store_slots(double* q, const double* v) {
+  if constexpr (NT) {
+    const d2v_st a = {v[0], v[1]}, b = {v[2], v[3]};
+    __builtin_nontemporal_store(a, reinterpret_cast<d2v_st*>(q));
+    __builtin_nontemporal_store(b, reinterpret_cast<d2v_st*>(q) + 1);
+  } else {
+    reinterpret_cast<double2*>(q)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2*>(q)[1] = make_double2(v[2], v[3]);
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void store_slots(float* q, const double* v) {
+  if constexpr (NT) {
+    const f4v_st a = {float(v[0]), float(v[1]), float(v[2]), float(v[3])};
+    __builtin_nontemporal_store(a, reinterpret_cast<f4v_st*>(q));
+  } else {
+    *reinterpret_cast<float4*>(q) = make_float4(float(v[0]), float(v[1]), float(v[2]), float(v[3]));
+  }
+}
+
 constexpr int kLP = 4;  // complex lines per unit (slot r of both lines, r = 0..3)
 
 // One unit per workgroup: workgroup b runs on XCD b % 8, so units 2x and
@@ -491,7 +519,10 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
       const double dv[4] = {odd ? r0 : z0.re, odd ? r1 : z1.re, odd ? z0.im : r0, odd ? z1.im : r1};
       if (it == 1 && !d.has1) continue;
       T* q = out + it * ls + (int64_t)i * ps;
-      if constexpr (sizeof(T) == 8) {
+      if constexpr (N <= kLongLine) {
+        const double sv[4] = {c4[0] * dv[0], c4[1] * dv[1], c4[2] * dv[2], c4[3] * dv[3]};
+        store_slots<sizeof(T) == 4 || ADJ>(q, sv);
+      } else if constexpr (sizeof(T) == 8) {
         reinterpret_cast<double2*>(q)[0] = make_double2(c4[0] * dv[0], c4[1] * dv[1]);
         reinterpret_cast<double2*>(q)[1] = make_double2(c4[2] * dv[2], c4[3] * dv[3]);
       } else {
