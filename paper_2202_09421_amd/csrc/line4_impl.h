@@ -50,13 +50,14 @@ struct Lines4Args {
   int dir_first;           // direction of units [0, units_first)
   int units_first;
   int nunits;
+  int nt_out;              // plan streams its state arrays (non-temporal stores where they pay)
 };
 
 // Store of one (point, line) lane's 4 slots (lengths up to kLongLine).  NT:
-// with the non-temporal hint (the outputs are not read again by the pass).
-// Measured at N_p = 540: 11 % faster FP32 passes, 1 % faster FP64
-// transposes, but a 5 % slower FP64 forward pass, which keeps ordinary
-// stores.
+// with the non-temporal hint (the outputs are not read again by the pass),
+// for plans that stream their state arrays.  Measured at N_p = 540: 11 %
+// faster FP32 passes, 1 % faster FP64 transposes, but a 5 % slower FP64
+// forward pass, which keeps ordinary stores.
 typedef double d2v_st __attribute__((ext_vector_type(2)));
 typedef float f4v_st __attribute__((ext_vector_type(4)));
 template <bool NT>
@@ -521,7 +522,12 @@ __device__ __forceinline__ void transform_unit(const Lines4Args<T>& a, const Uni
       T* q = out + it * ls + (int64_t)i * ps;
       if constexpr (N <= kLongLine) {
         const double sv[4] = {c4[0] * dv[0], c4[1] * dv[1], c4[2] * dv[2], c4[3] * dv[3]};
-        store_slots<sizeof(T) == 4 || ADJ>(q, sv);
+        if constexpr (sizeof(T) == 4 || ADJ) {
+          if (a.nt_out) store_slots<true>(q, sv);
+          else store_slots<false>(q, sv);
+        } else {
+          store_slots<false>(q, sv);
+        }
       } else if constexpr (sizeof(T) == 8) {
         reinterpret_cast<double2*>(q)[0] = make_double2(c4[0] * dv[0], c4[1] * dv[1]);
         reinterpret_cast<double2*>(q)[1] = make_double2(c4[2] * dv[2], c4[3] * dv[3]);

@@ -129,6 +129,7 @@ static hipError_t launch4_t(const Plan& p, const LineLaunch& L, hipStream_t s) {
   a.grp_stride = p.grp_stride;
   a.inst_stride = p.inst_stride;
   a.G = (int)p.G;
+  a.nt_out = p.stream_nt ? 1 : 0;
   const bool dx = (L.dirs & 1) != 0, dy = (L.dirs & 2) != 0;
   a.dir_first = dx ? 0 : 1;
   a.fc = dx ? p.fcx : p.fcy;

@@ -142,24 +142,29 @@ __device__ __forceinline__ typename Mfma<T>::acc_t scatter_tile(const T* Bs, con
 
 // Element access at a 32-bit byte offset from a per-block base pointer: the
 // base stays in scalar registers and one offset register serves every array
-// (one instance of a state is below 4 GiB; checked by the plan).  The state
-// arrays are streamed: every element is read or written once per launch and
-// the arrays far exceed the caches, so the accesses carry the non-temporal
-// hint (5 % faster node passes at 513 x 513 x 64, FP64).
-template <typename T>
+// (one instance of a state is below 4 GiB; checked by the plan).  Every
+// element is read or written once per launch.  NT (plans whose state arrays
+// are far larger than the 256 MiB memory-side cache): the accesses carry the
+// non-temporal hint, 5-7 % faster node passes at 513 x 513 x 64; on arrays
+// the cache holds between launches (257 x 257 x 32) the hint costs 3-8 %.
+template <bool NT, typename T>
 __device__ __forceinline__ T ldo(const T* base, uint32_t boff) {
   const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
-  if constexpr (std::is_same<T, float4>::value) {
+  if constexpr (!NT) {
+    return *p;
+  } else if constexpr (std::is_same<T, float4>::value) {
     const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
     return make_float4(v.x, v.y, v.z, v.w);
   } else {
     return __builtin_nontemporal_load(p);
   }
 }
-template <typename T>
+template <bool NT, typename T>
 __device__ __forceinline__ void sto(T* base, uint32_t boff, T v) {
   T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff);
-  if constexpr (std::is_same<T, float4>::value) {
+  if constexpr (!NT) {
+    *p = v;
+  } else if constexpr (std::is_same<T, float4>::value) {
     const f4v w = {v.x, v.y, v.z, v.w};
     __builtin_nontemporal_store(w, reinterpret_cast<f4v*>(p));
   } else {
@@ -169,25 +174,25 @@ __device__ __forceinline__ void sto(T* base, uint32_t boff, T v) {
 
 // The lane's 4 values of one array: per-value offsets off[v] (FP64) or one
 // 16-byte vector at off[0] (FP32); ok[v] masks the values.
-template <typename T>
+template <bool NT, typename T>
 __device__ __forceinline__ void ld4(const T* base, const uint32_t* off, const bool* ok, T* x) {
   if constexpr (kVecLane<T>) {
     float4 q = {0.f, 0.f, 0.f, 0.f};
-    if (ok[0]) q = ldo(reinterpret_cast<const float4*>(base), off[0]);
+    if (ok[0]) q = ldo<NT>(reinterpret_cast<const float4*>(base), off[0]);
     x[0] = q.x; x[1] = q.y; x[2] = q.z; x[3] = q.w;
   } else {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = ok[v] ? ldo(base, off[v]) : T(0);
+    for (int v = 0; v < 4; ++v) x[v] = ok[v] ? ldo<NT>(base, off[v]) : T(0);
   }
 }
-template <typename T>
+template <bool NT, typename T>
 __device__ __forceinline__ void st4(T* base, const uint32_t* off, const bool* ok, const T* x) {
   if constexpr (kVecLane<T>) {
-    if (ok[0]) sto(reinterpret_cast<float4*>(base), off[0], make_float4(x[0], x[1], x[2], x[3]));
+    if (ok[0]) sto<NT>(reinterpret_cast<float4*>(base), off[0], make_float4(x[0], x[1], x[2], x[3]));
   } else {
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      if (ok[v]) sto(base, off[v], x[v]);
+      if (ok[v]) sto<NT>(base, off[v], x[v]);
   }
 }
 // Lane offsets and masks of the 4 values.
@@ -266,7 +271,7 @@ __device__ __forceinline__ double sep_value(const rte_separable& f, int row, int
   return acc;
 }
 
-template <typename T, int RTC, int MODE>
+template <typename T, int RTC, int MODE, bool NT>
 __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwdArgs<T> a) {
   constexpr bool CADJ = MODE == 1;
   constexpr bool EXT = MODE == 2;
@@ -291,12 +296,12 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
   bool gv[4];
   lane_offsets<T>(G, t, off, gv);
   if constexpr (kVecLane<T>) {
-    ld4(uq, off, gv, u);
-    ld4(Xq, off, gv, X);
-    ld4(Yq, off, gv, Y);
-    ld4(L1q, off, gv, L1);
-    ld4(L2q, off, gv, L2);
-    ld4(L3q, off, gv, L3);
+    ld4<NT>(uq, off, gv, u);
+    ld4<NT>(Xq, off, gv, X);
+    ld4<NT>(Yq, off, gv, Y);
+    ld4<NT>(L1q, off, gv, L1);
+    ld4<NT>(L2q, off, gv, L2);
+    ld4<NT>(L3q, off, gv, L3);
   } else {
     // value by value, all arrays of one value together (this issue order
     // streams measurably faster than array by array)
@@ -304,9 +309,9 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
     for (int v = 0; v < 4; ++v) {
       u[v] = X[v] = Y[v] = L1[v] = L2[v] = L3[v] = up[v] = T(0);
       if (gv[v]) {
-        u[v] = ldo(uq, off[v]); X[v] = ldo(Xq, off[v]); Y[v] = ldo(Yq, off[v]);
-        L1[v] = ldo(L1q, off[v]); L2[v] = ldo(L2q, off[v]); L3[v] = ldo(L3q, off[v]);
-        if constexpr (CADJ) up[v] = ldo(a.upair + ib, pair_offset<T>(G, t, a.slot_rev, v));
+        u[v] = ldo<NT>(uq, off[v]); X[v] = ldo<NT>(Xq, off[v]); Y[v] = ldo<NT>(Yq, off[v]);
+        L1[v] = ldo<NT>(L1q, off[v]); L2[v] = ldo<NT>(L2q, off[v]); L3[v] = ldo<NT>(L3q, off[v]);
+        if constexpr (CADJ) up[v] = ldo<NT>(a.upair + ib, pair_offset<T>(G, t, a.slot_rev, v));
       }
     }
   }
@@ -315,7 +320,7 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
     for (int v = 0; v < 4; ++v) {
       up[v] = T(0);
       if constexpr (CADJ) {
-        if (gv[v]) up[v] = ldo(a.upair + ib, pair_offset<T>(G, t, a.slot_rev, v));
+        if (gv[v]) up[v] = ldo<NT>(a.upair + ib, pair_offset<T>(G, t, a.slot_rev, v));
       }
     }
   }
@@ -347,10 +352,10 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
     if constexpr (EXT) Ln[v] += qv[v];
     un[v] = u[v] + cdt * (T(kChi0) * Ln[v] + T(kChi1) * L1[v] + T(kChi2) * L2[v] + T(kChi3) * L3[v]);
     if constexpr (!kVecLane<T>) {
-      if (gv[v]) sto(Loq, off[v], Ln[v]);
+      if (gv[v]) sto<NT>(Loq, off[v], Ln[v]);
     }
   }
-  if constexpr (kVecLane<T>) st4(Loq, off, gv, Ln);
+  if constexpr (kVecLane<T>) st4<NT>(Loq, off, gv, Ln);
 
   // inflow condition with Fresnel reflection and the beams at t_{n+1}.  The
   // boundary tables (reflection rules, beam factors, detector weights) of the
@@ -407,7 +412,7 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_fwd_kernel(NodeFwd
     pw0 += __shfl_xor(pw0, 32);
     pw1 += __shfl_xor(pw1, 32);
   }
-  st4(uoq, off, gv, un);
+  st4<NT>(uoq, off, gv, un);
 
   if constexpr (CADJ) {
     double pa = 0.0, pb = 0.0;
@@ -476,7 +481,7 @@ struct NodeAdjArgs {
 };
 
 // ap1 is read (P1^{n+1}) and overwritten (P1^n) element by element by one lane.
-template <typename T, int RTC>
+template <typename T, int RTC, bool NT>
 __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdjArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const NodeGeom& G = a.geo;
@@ -501,21 +506,21 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
   bool gv[4];
   lane_offsets<T>(G, t, off, gv);
   if constexpr (kVecLane<T>) {
-    ld4(txq, off, gv, tx);
-    ld4(tyq, off, gv, ty);
-    ld4(static_cast<const T*>(p1q), off, gv, p1);
-    ld4(v2q, off, gv, v2);
-    ld4(v3q, off, gv, v3);
-    ld4(v4q, off, gv, v4);
-    ld4(uq, off, gv, uu);
+    ld4<NT>(txq, off, gv, tx);
+    ld4<NT>(tyq, off, gv, ty);
+    ld4<NT>(static_cast<const T*>(p1q), off, gv, p1);
+    ld4<NT>(v2q, off, gv, v2);
+    ld4<NT>(v3q, off, gv, v3);
+    ld4<NT>(v4q, off, gv, v4);
+    ld4<NT>(uq, off, gv, uu);
   } else {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       tx[v] = ty[v] = p1[v] = v2[v] = v3[v] = v4[v] = uu[v] = T(0);
       if (gv[v]) {
-        tx[v] = ldo(txq, off[v]); ty[v] = ldo(tyq, off[v]); p1[v] = ldo(p1q, off[v]);
-        v2[v] = ldo(v2q, off[v]); v3[v] = ldo(v3q, off[v]); v4[v] = ldo(v4q, off[v]);
-        uu[v] = ldo(uq, off[v]);
+        tx[v] = ldo<NT>(txq, off[v]); ty[v] = ldo<NT>(tyq, off[v]); p1[v] = ldo<NT>(p1q, off[v]);
+        v2[v] = ldo<NT>(v2q, off[v]); v3[v] = ldo<NT>(v3q, off[v]); v4[v] = ldo<NT>(v4q, off[v]);
+        uu[v] = ldo<NT>(uq, off[v]);
       }
     }
   }
@@ -599,18 +604,18 @@ __global__ __launch_bounds__(RTC == 0 ? 1024 : 512) void node_adj_kernel(NodeAdj
     pn[v] = v1[v] + cdtT * (B * S[v] - (A + B) * w[v]) + injv[v];
     if constexpr (!kVecLane<T>) {
       if (gv[v]) {
-        sto(p1q, off[v], pn[v]);
-        sto(wq, off[v], w[v]);
-        sto(v1q, off[v], v1[v]);
+        sto<NT>(p1q, off[v], pn[v]);
+        sto<NT>(wq, off[v], w[v]);
+        sto<NT>(v1q, off[v], v1[v]);
       }
     }
     pa += (double)uu[v] * (double)w[v];
     pb += (double)uu[v] * ((double)S[v] - (double)w[v]);
   }
   if constexpr (kVecLane<T>) {
-    st4(p1q, off, gv, pn);
-    st4(wq, off, gv, w);
-    st4(v1q, off, gv, v1);
+    st4<NT>(p1q, off, gv, pn);
+    st4<NT>(wq, off, gv, w);
+    st4<NT>(v1q, off, gv, v1);
   }
   pa += __shfl_xor(pa, 16);
   pb += __shfl_xor(pb, 16);
@@ -672,23 +677,29 @@ static dim3 node_grid(const Plan& p, const NodeGeom& g) {
   return dim3((unsigned)((tiles + g.NT - 1) / g.NT), (unsigned)p.cnq);
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool NT>
 static void launch_node_fwd_rt(const NodeFwdArgs<T>& a, dim3 grid, dim3 block, size_t sh, hipStream_t s) {
   switch (a.geo.RT) {
-    case 1: hipLaunchKernelGGL((node_fwd_kernel<T, 1, MODE>), grid, block, sh, s, a); break;
-    case 2: hipLaunchKernelGGL((node_fwd_kernel<T, 2, MODE>), grid, block, sh, s, a); break;
-    case 3: hipLaunchKernelGGL((node_fwd_kernel<T, 3, MODE>), grid, block, sh, s, a); break;
-    case 4: hipLaunchKernelGGL((node_fwd_kernel<T, 4, MODE>), grid, block, sh, s, a); break;
-    default: hipLaunchKernelGGL((node_fwd_kernel<T, 0, MODE>), grid, block, sh, s, a); break;
+    case 1: hipLaunchKernelGGL((node_fwd_kernel<T, 1, MODE, NT>), grid, block, sh, s, a); break;
+    case 2: hipLaunchKernelGGL((node_fwd_kernel<T, 2, MODE, NT>), grid, block, sh, s, a); break;
+    case 3: hipLaunchKernelGGL((node_fwd_kernel<T, 3, MODE, NT>), grid, block, sh, s, a); break;
+    case 4: hipLaunchKernelGGL((node_fwd_kernel<T, 4, MODE, NT>), grid, block, sh, s, a); break;
+    default: hipLaunchKernelGGL((node_fwd_kernel<T, 0, MODE, NT>), grid, block, sh, s, a); break;
   }
 }
 
+template <typename T, bool NT>
+static void launch_node_fwd_nt(int mode, const NodeFwdArgs<T>& a, dim3 grid, dim3 block, size_t sh, hipStream_t s) {
+  if (mode == 1) launch_node_fwd_rt<T, 1, NT>(a, grid, block, sh, s);
+  else if (mode == 2) launch_node_fwd_rt<T, 2, NT>(a, grid, block, sh, s);
+  else launch_node_fwd_rt<T, 0, NT>(a, grid, block, sh, s);
+}
+
 template <typename T>
-static hipError_t launch_node_fwd_mode(int mode, const NodeFwdArgs<T>& a, dim3 grid, dim3 block, size_t sh,
+static hipError_t launch_node_fwd_mode(int mode, bool nt, const NodeFwdArgs<T>& a, dim3 grid, dim3 block, size_t sh,
                                        hipStream_t s) {
-  if (mode == 1) launch_node_fwd_rt<T, 1>(a, grid, block, sh, s);
-  else if (mode == 2) launch_node_fwd_rt<T, 2>(a, grid, block, sh, s);
-  else launch_node_fwd_rt<T, 0>(a, grid, block, sh, s);
+  if (nt) launch_node_fwd_nt<T, true>(mode, a, grid, block, sh, s);
+  else launch_node_fwd_nt<T, false>(mode, a, grid, block, sh, s);
   return hipGetLastError();
 }
 
@@ -715,11 +726,22 @@ static hipError_t node_fwd_t(const Plan& p, const NodeFwdLaunch& L, hipStream_t 
   if (L.csrc && (!L.upair || !L.ga || !L.gb || L.flux || L.vsrc || L.inflow)) return hipErrorInvalidValue;
   const int mode = L.csrc ? 1 : ((L.vsrc || L.inflow) ? 2 : 0);
   if (mode == 2 && (L.step < -3 || L.step >= p.K)) return hipErrorInvalidValue;
-  return launch_node_fwd_mode<T>(mode, a, grid, block, sh, s);
+  return launch_node_fwd_mode<T>(mode, p.stream_nt, a, grid, block, sh, s);
 }
 
 hipError_t launch_node_fwd(const Plan& p, const NodeFwdLaunch& L, hipStream_t s) {
   return p.dtype == RTE_F64 ? node_fwd_t<double>(p, L, s) : node_fwd_t<float>(p, L, s);
+}
+
+template <typename T, bool NT>
+static void launch_node_adj_rt(const NodeAdjArgs<T>& a, dim3 grid, dim3 block, size_t sh, hipStream_t s) {
+  switch (a.geo.RT) {
+    case 1: hipLaunchKernelGGL((node_adj_kernel<T, 1, NT>), grid, block, sh, s, a); break;
+    case 2: hipLaunchKernelGGL((node_adj_kernel<T, 2, NT>), grid, block, sh, s, a); break;
+    case 3: hipLaunchKernelGGL((node_adj_kernel<T, 3, NT>), grid, block, sh, s, a); break;
+    case 4: hipLaunchKernelGGL((node_adj_kernel<T, 4, NT>), grid, block, sh, s, a); break;
+    default: hipLaunchKernelGGL((node_adj_kernel<T, 0, NT>), grid, block, sh, s, a); break;
+  }
 }
 
 template <typename T>
@@ -735,13 +757,8 @@ static hipError_t node_adj_t(const Plan& p, const NodeAdjLaunch& L, hipStream_t 
   a.cdt = p.prob.c * p.prob.dt;
   const dim3 grid = node_grid(p, a.geo), block((unsigned)(64 * a.geo.NT * a.geo.RT));
   const size_t sh = node_shmem(a.geo, sizeof(T));
-  switch (a.geo.RT) {
-    case 1: hipLaunchKernelGGL((node_adj_kernel<T, 1>), grid, block, sh, s, a); break;
-    case 2: hipLaunchKernelGGL((node_adj_kernel<T, 2>), grid, block, sh, s, a); break;
-    case 3: hipLaunchKernelGGL((node_adj_kernel<T, 3>), grid, block, sh, s, a); break;
-    case 4: hipLaunchKernelGGL((node_adj_kernel<T, 4>), grid, block, sh, s, a); break;
-    default: hipLaunchKernelGGL((node_adj_kernel<T, 0>), grid, block, sh, s, a); break;
-  }
+  if (p.stream_nt) launch_node_adj_rt<T, true>(a, grid, block, sh, s);
+  else launch_node_adj_rt<T, false>(a, grid, block, sh, s);
   return hipGetLastError();
 }
 

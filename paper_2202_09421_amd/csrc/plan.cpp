@@ -327,6 +327,7 @@ int plan_create(const rte_problem* prob, const rte_beam* beams, int64_t n_beams,
   p.chunk = (prob->combo_chunk > 0) ? std::min<int64_t>(prob->combo_chunk, p.Nq) : p.Nq;
   p.cq0 = 0;
   p.cnq = p.chunk;
+  p.stream_nt = p.chunk * p.inst_stride * (prob->dtype == RTE_F64 ? 8 : 4) > kStreamNtBytes;
   const int M = (int)p.M;
   const double dx = (prob->xmax - prob->xmin) / prob->Nx;
   const double dy = (prob->ymax - prob->ymin) / prob->Ny;

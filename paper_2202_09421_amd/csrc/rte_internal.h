@@ -14,6 +14,11 @@ namespace rte {
 constexpr int kGroup = 4;        // ordinate slots per storage group (one reflection orbit)
 constexpr int kMaxPasses = 12;   // FFT passes (radices 2,3,4,5)
 constexpr int kMaxFcD = 8;       // matching points supported
+// state arrays (one chunk) above this size are streamed with the
+// non-temporal hint: a node pass then moves 8-10 such arrays, well beyond
+// the 256 MiB memory-side cache that holds smaller plans' arrays between
+// launches
+constexpr int64_t kStreamNtBytes = int64_t(64) << 20;
 constexpr int kLineThreads = 128; // generic (Stockham) line kernel
 constexpr int kFcTab = 384;      // continuation matrix entries ((C+E) * 2d) staged by the four-step kernel
 constexpr int kLongLine = 600;   // four-step lengths above this read the continuation matrix from global memory
@@ -107,6 +112,9 @@ struct Plan {
   // sources [cq0, cq0 + cnq) of the current chunk (set by the orchestration)
   int64_t chunk = 1;
   mutable int64_t cq0 = 0, cnq = 1;
+  // one state array of a chunk exceeds kStreamNtBytes: the per-step kernels
+  // stream their state arrays with the non-temporal hint (set at create)
+  bool stream_nt = false;
   int64_t saved_chunk = -1;    // chunk whose forward states are in the workspace
   bool have_forward = false;   // a saved forward lives in the workspace
   int64_t saved_K = 0;
