@@ -62,7 +62,8 @@ TRAFFIC_ROWS = {
     "lines_fwd": "x and y line derivatives (fwd)", "node_fwd": "node pass (fwd)",
     "node_adj": "node pass (adj)", "lines_adj": "x and y line transposes (adj)",
 }
-TRAFFIC_FILE = {("mss", "f64"): "profiles/mss_fp64_513x513_M64_chunk4_hbm_traffic.md"}
+TRAFFIC_FILE = {("mss", "f64"): "profiles/mss_fp64_513x513_M64_chunk4_hbm_traffic.md",
+                ("mss", "f32"): "profiles/mss_fp32_513x513_M64_chunk8_hbm_traffic.md"}
 
 
 def source_hash():
